@@ -1,0 +1,216 @@
+/*
+ * lbmd.h -- C ABI of the MI355X (gfx950) coupled lattice-Boltzmann / bead-dynamics library.
+ *
+ * The library advances the hybrid scheme of Fyta, Melchionna, Kaxiras and Succi,
+ * "Coupling Lattice Boltzmann with Atomistic Dynamics for the multiscale
+ * simulation of nano-biological flows" (arXiv:0710.1272), Sec. II:
+ *   - a D3Q19 BGK lattice-Boltzmann solvent (Eq. lbe, f_eq eq.), with periodic or
+ *     specular free-slip outer faces and half-way bounce-back on solid nodes
+ *     (the separating wall with a square pore of Sec. III);
+ *   - bead chains moved by Langevin dynamics (Eq. force: harmonic bonds, WCA
+ *     bead-bead and bead-wall repulsion, a pulling force inside the pore,
+ *     frictional drag against the local fluid velocity, random force);
+ *   - the two-way coupling of Sec. II: nearest-grid-point velocity interpolation
+ *     at each bead, M MD substeps per LB step with that velocity frozen, and the
+ *     equal and opposite force spread back as the source S_p (S_p eq.).
+ * Any number of independent replicas (boxes of different sizes, each with its own
+ * chains and random seed) advance together.
+ *
+ * Conventions used throughout:
+ *   - Node index of (x,y,z) in a replica of nx*ny*nz nodes: x + nx*(y + ny*z).
+ *   - Populations p = 0..18 in the order: rest; +x,-x,+y,-y,+z,-z;
+ *     (+1,+1,0),(-1,-1,0),(+1,-1,0),(-1,+1,0),(+1,0,+1),(-1,0,-1),(+1,0,-1),
+ *     (-1,0,+1),(0,+1,+1),(0,-1,-1),(0,+1,-1),(0,-1,+1).
+ *   - Lattice units: Delta x = Delta t = 1; c_s^2 = 1/3; omega = 1/tau.
+ *   - Host arrays that cover several replicas hold the replicas back to back in
+ *     replica order, each block in the layout stated for one replica.
+ *   - Every call returns LB_OK (0) or a negative LB_E* code; on error,
+ *     lb_last_error_message() describes it.  No C++ exception crosses this ABI.
+ *   - All calls on one context must come from one host thread at a time.
+ */
+#ifndef LBMD_H
+#define LBMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------------ */
+#define LB_OK 0
+#define LB_EINVAL (-1)    /* invalid argument or configuration */
+#define LB_ENOMEM (-2)    /* device or host allocation failed */
+#define LB_EDEVICE (-3)   /* HIP runtime error, or no usable gfx950 device */
+#define LB_EUNSTABLE (-4) /* the device error word is set (see LB_ERR_* bits) */
+#define LB_ESTATE (-5)    /* call not valid in the context's current state */
+#define LB_ESIZE (-6)     /* caller buffer too small */
+
+/* bits of the device error word (reported through LB_MOM_STATUS) */
+#define LB_ERR_BEAD_IN_SOLID 1u   /* a bead centre lies inside a solid node cube */
+#define LB_ERR_BEAD_OUTSIDE 2u    /* a bead crossed a free-slip outer face */
+#define LB_ERR_NONFINITE 4u       /* a bead coordinate is not finite */
+#define LB_ERR_BOND_STRETCH 8u    /* a bond is longer than 2 r0 */
+#define LB_ERR_DENSITY 16u        /* a fluid node met rho <= 0 or a non-finite rho */
+
+/* ---- configuration ---------------------------------------------------------- */
+#define LB_BC_PERIODIC 0
+#define LB_BC_FREESLIP 1
+
+#define LB_STORE_F64 0     /* populations stored and collided in FP64 */
+#define LB_STORE_F32 1     /* populations stored and collided in FP32 */
+#define LB_STORE_F16DEV 2  /* FP16 store of s_p (f_p - w_p rho0), FP32 collision */
+#define LB_STORE_BF16DEV 3 /* BF16 store of s_p (f_p - w_p rho0), FP32 collision */
+
+#define LB_MAX_WALLS 2
+
+/* A separating wall (Sec. III): solid node planes x0..x1 over the whole
+ * cross-section, except the open pore y0..y1 x z0..z1 (no pore if y0 > y1). */
+typedef struct lbmd_wall {
+    int x0, x1;
+    int y0, y1;
+    int z0, z1;
+} lbmd_wall;
+
+typedef struct lbmd_replica {
+    int nx, ny, nz;        /* box size in nodes, each >= 2 */
+    int bc[3];             /* LB_BC_PERIODIC or LB_BC_FREESLIP per axis */
+    int n_walls;           /* 0..LB_MAX_WALLS */
+    lbmd_wall wall[LB_MAX_WALLS];
+    double tau;            /* BGK relaxation time, > 1/2 (nu = (tau - 1/2)/3, Sec. II) */
+    double rho0;           /* reference density; also the 16-bit deviation origin */
+    int n_chains;          /* number of linear chains */
+    const int* chain_len;  /* host, n_chains lengths >= 1; read during lb_init only */
+    uint64_t seed;         /* Philox key (low word, high word) of this replica */
+} lbmd_replica;
+
+/* Bead-model parameters shared by all replicas (Sec. II Eq. force; Sec. III). */
+typedef struct lbmd_md_params {
+    int M;             /* MD substeps per LB step, Delta t_MD = 1/M */
+    double mass;       /* bead mass m */
+    double gamma;      /* friction coefficient: F_drag = -m gamma (v - u) */
+    double kT;         /* temperature of the random force */
+    double k_bond;     /* harmonic bond k (r - r0)^2 / 2 between chain neighbours */
+    double r0;
+    double eps, sigma; /* WCA between non-bonded beads, cut at 2^(1/6) sigma */
+    double eps_w, sigma_w; /* WCA on the distance to the nearest solid surface / free-slip face */
+    double f_drive;    /* pulling force on beads whose nearest node is a pore node */
+    int drive_sign;    /* +1: along +x; -1: along -x */
+} lbmd_md_params;
+
+/* Optional initial state (host arrays, read during lb_init only). */
+typedef struct lbmd_initial_state {
+    const double* rho;    /* [V] per replica, or NULL for rho0 everywhere */
+    const double* u;      /* [3][V] per replica (u_x block, u_y, u_z), or NULL for rest */
+    const double* pops;   /* [19][V] per replica pre-collision populations; overrides rho/u */
+    const double* bead_r; /* [n_beads][3] per replica positions; required if there are beads */
+    const double* bead_v; /* [n_beads][3] per replica velocities, or NULL for rest */
+    int64_t step0;        /* initial value of the LB step counter (Philox counter word) */
+} lbmd_initial_state;
+
+#define LB_CFG_NO_GRAPH 1u   /* enqueue plain launches instead of captured HIP graphs */
+#define LB_CFG_AUTOTUNE 2u   /* time candidate launch shapes at lb_init and keep the fastest */
+
+typedef struct lbmd_config {
+    int n_replicas;
+    const lbmd_replica* replicas;      /* host array of n_replicas */
+    int storage;                       /* LB_STORE_* for every replica */
+    lbmd_md_params md;
+    const lbmd_initial_state* init;    /* may be NULL: rest fluid at rho0, no beads allowed */
+    int block_size;                    /* threads per block of the lattice kernel, 0 = default */
+    unsigned flags;                    /* LB_CFG_* */
+} lbmd_config;
+
+/* Device buffers.  Either all NULL-free (caller-owned, sizes from
+ * lb_required_bytes) or the whole struct pointer NULL (library-owned). */
+typedef struct lbmd_buffers {
+    void* pops[2]; /* device, lb_required_bytes(cfg, LB_BUF_POPS) bytes each, 256-byte aligned */
+    void* beads;   /* device, lb_required_bytes(cfg, LB_BUF_BEADS) bytes, 256-byte aligned */
+    void* work;    /* device, lb_required_bytes(cfg, LB_BUF_WORK) bytes, 256-byte aligned */
+} lbmd_buffers;
+
+#define LB_BUF_POPS 0
+#define LB_BUF_BEADS 1
+#define LB_BUF_WORK 2
+
+typedef struct lbmd_ctx lbmd_ctx;
+
+/* Bytes the caller must provide for buffer `which` (LB_BUF_*), 0 on an invalid
+ * configuration.  Pure host computation. */
+size_t lb_required_bytes(const lbmd_config* cfg, int which);
+
+/* Checks a configuration on the host, without touching the device.  Rejects
+ * tau <= 1/2, boxes below 2 nodes, walls or pores outside the box, walls closer
+ * than 2 nodes to a periodic x face, M < 1, an unstable bond/substep ratio
+ * (2 sqrt(k/m)/M >= 2, the kick-drift stability limit), chain lengths that do
+ * not add up, and unknown storage. Returns LB_OK or LB_EINVAL. */
+int lb_validate_config(const lbmd_config* cfg);
+
+/* Sec. II, the lattice-Boltzmann and bead state of every replica.
+ * Validates cfg, binds (or allocates) the device buffers, writes the initial
+ * populations (f_eq of the given rho/u, or the given pre-collision populations),
+ * uploads beads, optionally autotunes, and prepares the step sequence.
+ * hip_stream: a hipStream_t (NULL = default stream) on which every later call
+ * enqueues its work.  *out receives a library-owned context freed by lb_destroy.
+ * Synchronises the stream before returning. */
+int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, lbmd_ctx** out);
+
+#define LB_STEP_COUPLED 1u /* steps 1-4 of Sec. II; without it: lattice update only */
+
+/* Enqueues n_steps LB time steps (Eq. lbe with Delta t = 1).  With
+ * LB_STEP_COUPLED each step is: nearest-node velocity interpolation at the beads,
+ * M MD substeps with that velocity frozen, then the lattice update with the
+ * spread reaction force S_p = -(w_p / c_s^2) Fbar_i . c_p added after collision
+ * at each bead's node (Fbar_i = mean over the substeps of drag + random force).
+ * Without it, only the lattice stream-and-collide runs.  Asynchronous: returns
+ * launch errors only. */
+int lb_step(lbmd_ctx* ctx, int n_steps, unsigned flags);
+
+#define LB_COUPLE_INTERP 1u /* step 1 of Sec. II alone: u(x) -> u_i, nearest node of each bead */
+#define LB_COUPLE_SPREAD 2u /* step 3 alone: add the spread reaction of the last MD call's Fbar */
+
+/* One half of the coupling, for checking each half separately.  INTERP reads
+ * the current pre-collision state; SPREAD adds S_p to the current (post-collision,
+ * not yet streamed) state at the nodes found by the last INTERP.  The sequence
+ * INTERP, md_step, lb_step(1, 0), SPREAD equals one coupled step.  Asynchronous. */
+int lb_couple(lbmd_ctx* ctx, unsigned dir);
+
+/* Step 2 of Sec. II alone: M substeps of every replica's beads with the fluid
+ * velocity of the last INTERP frozen; accumulates Fbar.  Asynchronous. */
+int md_step(lbmd_ctx* ctx);
+
+#define LB_MOM_CONSERVED 1u   /* 4 doubles: total mass, momentum x, y, z over fluid nodes (FP64) */
+#define LB_MOM_FIELDS 2u      /* [4][V] doubles: rho, u_x, u_y, u_z per node (0 on solid nodes) */
+#define LB_MOM_POPULATIONS 3u /* [19][V] doubles: pre-collision populations (0 on solid nodes) */
+#define LB_MOM_BEADS 4u       /* [n][3] positions then [n][3] velocities, doubles */
+#define LB_MOM_TRANSLOC 5u    /* 6 doubles: N_T, completion step (-1 if none), COM x, y, z, step */
+#define LB_MOM_COUPLING 6u    /* [n][3] u_i, [n][3] Fbar_i, [n] node index (-1 on solid), doubles */
+#define LB_MOM_STATUS 7u      /* 2 doubles: device error word, LB step counter */
+
+/* Observables of one replica (Sec. II Eqs. dens and vel; Sec. III translocation
+ * coordinate).  Synchronises the stream and copies into host_out (bytes long).
+ * Returns LB_ESIZE if bytes is too small, LB_EUNSTABLE if the device error word
+ * is non-zero (the output is still written), LB_OK otherwise. */
+int lb_moments(lbmd_ctx* ctx, int replica, unsigned what, void* host_out, size_t bytes);
+
+/* Bytes lb_moments needs for (replica, what); 0 if invalid. */
+size_t lb_moments_bytes(const lbmd_ctx* ctx, int replica, unsigned what);
+
+/* Lattice-kernel launch shape in use (threads per block). */
+int lb_block_size(const lbmd_ctx* ctx);
+
+/* Synchronises the stream, frees library-owned buffers and the context. */
+int lb_destroy(lbmd_ctx* ctx);
+
+/* Static description of an error code. */
+const char* lb_strerror(int code);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* lb_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMD_H */

@@ -35,6 +35,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define Q 19
 
@@ -708,3 +711,13 @@ void ora_lattice(int* c, double* w, int* opp)
 }
 
 double ora_cs2(void) { return CS2; }
+
+/* number of threads the LB loop uses (1 without OpenMP) */
+int ora_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -84,6 +84,7 @@ def lib():
                                        lp, C.c_uint32, C.c_uint64]
         L.ora_lattice.argtypes = [ip, dp, ip]
         L.ora_cs2.restype = C.c_double
+        L.ora_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -130,6 +131,10 @@ def lattice():
     opp = np.zeros(Q, dtype=np.int32)
     lib().ora_lattice(_ip(c), _dp(w), _ip(opp))
     return c, w, opp
+
+
+def threads() -> int:
+    return lib().ora_threads()
 
 
 def cs2() -> float:

@@ -1,0 +1,477 @@
+// lb_kernels.hip -- lattice kernels (gfx950).
+//
+// k_stream_collide: one LB time step (arXiv:0710.1272 Sec. II, Eq. lbe with F_p = 0;
+// the source S_p is added afterwards by the spread kernel) in pull form.  Each thread
+// owns one node: it gathers the 19 post-collision populations that stream into the
+// node (periodic wrap, specular free-slip faces, half-way bounce-back on solid nodes),
+// forms rho and j (Eqs. dens, vel), relaxes towards f_eq (f_eq eq.) with
+// omega = 1/tau, and writes its own 19 post-collision values, coalesced and
+// non-temporal.  Per replica the populations form a [19][V] block with x fastest;
+// 16-bit storage keeps s_p (f_p - w_p rho0).  HBM traffic per fluid node is
+// 19 loads + 19 stores of the storage type, the kernel's roofline.
+#include <utility>
+
+#include "lbmd_internal.hpp"
+
+namespace lbmd {
+
+template <class F, int... Ps>
+__device__ __forceinline__ void for_pops_impl(F&& f, std::integer_sequence<int, Ps...>) {
+    (f(std::integral_constant<int, Ps>{}), ...);
+}
+template <class F>
+__device__ __forceinline__ void for_pops(F&& f) {
+    for_pops_impl(f, std::make_integer_sequence<int, Q>{});
+}
+
+// Blocks are dealt round-robin to the 8 XCDs; give each XCD one contiguous run of
+// tiles so that neighbouring tiles, which share the cache lines at their edges,
+// meet in the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+    const int per = G >> 3, rem = G & 7, j = b & 7;
+    return j * per + (j < rem ? j : rem) + (b >> 3);
+}
+
+__device__ __forceinline__ int replica_of_tile(const int* __restrict__ prefix, int n_reps, int tile) {
+    int lo = 0, hi = n_reps - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+enum GatherKind { G_FAST = 0, G_WALL = 1, G_GENERIC = 2 };
+
+// Incoming populations of one lane.
+//  G_GENERIC: any lane (full resolver, used by waves touching a y/z face);
+//  G_WALL:    y and z interior, lanes may neighbour a wall (solid test per source);
+//  G_FAST:    y and z interior, no wall within one node (only x faces need care).
+template <int S, int KIND>
+__device__ __forceinline__ void gather19(const Replica& R, const typename Codec<S>::T* __restrict__ src,
+                                         int idx, int x, int y, int z, typename Codec<S>::R* f) {
+    using C = Codec<S>;
+    const long long V = R.V;
+    const int nx = R.nx, nxy = R.nx * R.ny;
+    const typename C::T* __restrict__ base = src + R.pop_base;
+    // per-wall 3-bit masks: bit (d+1) set when x+d is a wall plane / y+d, z+d in the pore
+    unsigned mx[LB_MAX_WALLS] = {0u, 0u}, mp[LB_MAX_WALLS] = {0u, 0u};
+    if constexpr (KIND == G_WALL) {
+        for (int k = 0; k < R.n_walls; ++k) {
+            const int* w = R.wall[k];
+            unsigned bx = 0, by = 0, bz = 0;
+#pragma unroll
+            for (int d = -1; d <= 1; ++d) {
+                bx |= (unsigned)(x + d >= w[0] && x + d <= w[1]) << (d + 1);
+                by |= (unsigned)(y + d >= w[2] && y + d <= w[3]) << (d + 1);
+                bz |= (unsigned)(z + d >= w[4] && z + d <= w[5]) << (d + 1);
+            }
+            mx[k] = bx;
+            // pore membership of (y+dy, z+dz) for the 9 combinations, bit 3*(dy+1)+(dz+1)
+            unsigned m = 0;
+            if (pore_open(w)) {
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                    for (int dz = 0; dz < 3; ++dz)
+                        m |= (((by >> dy) & (bz >> dz)) & 1u) << (3 * dy + dz);
+            }
+            mp[k] = m;
+        }
+    }
+    for_pops([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        constexpr int cx = cx_of(p), cy = cy_of(p), cz = cz_of(p);
+        int node, q;
+        if constexpr (KIND == G_GENERIC) {
+            node = pull_source<p>(R, x, y, z, &q);
+        } else {
+            q = p;
+            node = idx - (cx + cy * nx + cz * nxy);
+            if constexpr (cx == 1) {
+                if (x == 0) {
+                    constexpr int m = mirror_of(p, 0);
+                    if (R.fs[0]) { node += 1; q = m; }
+                    else node += nx;
+                }
+            }
+            if constexpr (cx == -1) {
+                if (x == nx - 1) {
+                    constexpr int m = mirror_of(p, 0);
+                    if (R.fs[0]) { node -= 1; q = m; }
+                    else node -= nx;
+                }
+            }
+            if constexpr (KIND == G_WALL && p != 0) {
+                // source offset is -c: bit (1 - c) of each mask
+                bool solid = false;
+                for (int k = 0; k < R.n_walls; ++k) {
+                    bool inx = (mx[k] >> (1 - cx)) & 1u;
+                    bool inpore = (mp[k] >> (3 * (1 - cy) + (1 - cz))) & 1u;
+                    solid = solid || (inx && !inpore);
+                }
+                if (solid) { node = idx; q = opp_of(p); }
+            }
+        }
+        // q differs from p only by reflections or reversal, which keep the weight
+        // class, so the codec scale of p applies to slot q
+        f[p] = C::template load<p>(base[(long long)q * V + node]);
+    });
+}
+
+// BGK relaxation of one node, in place on f (full populations or deviations).
+template <int S>
+__device__ __forceinline__ typename Codec<S>::R collide(typename Codec<S>::R* f,
+                                                        typename Codec<S>::R omega,
+                                                        typename Codec<S>::R rho0) {
+    using Rl = typename Codec<S>::R;
+    Rl m0 = 0, jx = 0, jy = 0, jz = 0;
+    for_pops([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        m0 += f[p];
+        if constexpr (cx_of(p) == 1) jx += f[p];
+        if constexpr (cx_of(p) == -1) jx -= f[p];
+        if constexpr (cy_of(p) == 1) jy += f[p];
+        if constexpr (cy_of(p) == -1) jy -= f[p];
+        if constexpr (cz_of(p) == 1) jz += f[p];
+        if constexpr (cz_of(p) == -1) jz -= f[p];
+    });
+    // deviation storage: m0 = rho - rho0 and f_eq - w rho0 = w (m0 + rho (...))
+    const Rl rho = Codec<S>::deviation ? rho0 + m0 : m0;
+    const Rl inv = Rl(1) / rho;
+    const Rl ux = jx * inv, uy = jy * inv, uz = jz * inv;
+    const Rl usq = Rl(1.5) * (ux * ux + uy * uy + uz * uz);
+    for_pops([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        constexpr Rl w = w_of<Rl>(p);
+        Rl cu = 0;
+        if constexpr (cx_of(p) != 0) cu += Rl(cx_of(p)) * ux;
+        if constexpr (cy_of(p) != 0) cu += Rl(cy_of(p)) * uy;
+        if constexpr (cz_of(p) != 0) cu += Rl(cz_of(p)) * uz;
+        const Rl poly = Rl(3) * cu + Rl(4.5) * cu * cu - usq;
+        Rl feq;
+        if constexpr (Codec<S>::deviation) feq = w * (m0 + rho * poly);
+        else feq = w * rho * (Rl(1) + poly);
+        f[p] = f[p] + omega * (feq - f[p]);
+    });
+    return rho;
+}
+
+template <int S, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_stream_collide(const Replica* __restrict__ reps,
+                                                          const int* __restrict__ prefix,
+                                                          int n_reps,
+                                                          const typename Codec<S>::T* __restrict__ src,
+                                                          typename Codec<S>::T* __restrict__ dst,
+                                                          RunState* __restrict__ st, int bump_step) {
+    using C = Codec<S>;
+    using Rl = typename C::R;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int r = replica_of_tile(prefix, n_reps, tile);
+    const Replica& R = reps[r];
+    const int idx = (tile - prefix[r]) * BLOCK + threadIdx.x;
+    bool active = idx < R.V;
+    const uint32_t t = fdiv((uint32_t)idx, R.div_nx);
+    const int x = idx - (int)t * R.nx;
+    const uint32_t zz = fdiv(t, R.div_ny);
+    const int y = (int)t - (int)zz * R.ny;
+    const int z = (int)zz;
+    bool face = false, zone = false;
+    if (active) {
+        if (is_solid(R, x, y, z)) active = false;
+        face = y == 0 || y == R.ny - 1 || z == 0 || z == R.nz - 1;
+        for (int k = 0; k < R.n_walls; ++k) zone = zone || (x >= R.wall[k][0] - 1 && x <= R.wall[k][1] + 1);
+    }
+    face = face && active;
+    zone = zone && active;
+    const bool any_face = __ballot(face) != 0;
+    const bool any_zone = __ballot(zone) != 0;
+    if (bump_step && blockIdx.x == 0 && threadIdx.x == 0) st->step += 1;
+    if (!active) return;
+
+    Rl f[Q];
+    if (any_face) gather19<S, G_GENERIC>(R, src, idx, x, y, z, f);
+    else if (any_zone) gather19<S, G_WALL>(R, src, idx, x, y, z, f);
+    else gather19<S, G_FAST>(R, src, idx, x, y, z, f);
+
+    const Rl rho = collide<S>(f, (Rl)R.omega, (Rl)R.rho0);
+    if (!(rho > Rl(0)) || !(rho < Rl(1e30))) atomicOr(&st->err, LB_ERR_DENSITY);
+
+    typename C::T* __restrict__ out = dst + R.pop_base + idx;
+    const long long V = R.V;
+    for_pops([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        __builtin_nontemporal_store(C::template store<p>(f[p]), out + (long long)p * V);
+    });
+}
+
+// ---------------------------------------------------------------------------------
+// Initial state: a post-collision buffer whose pull reproduces wanted pre-collision
+// populations f0 (given, or f_eq of given rho/u, or w_p rho0).  Slot (s, q) holds
+// f0 at the push target (x, p) of (s, q).
+// ---------------------------------------------------------------------------------
+// f_eq of Sec. II for all 19 populations (c_s^2 = 1/3), in FP64
+__device__ __forceinline__ void feq19(double rho, double ux, double uy, double uz, double* feq) {
+    const double usq = 1.5 * (ux * ux + uy * uy + uz * uz);
+    for_pops([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        const double cu = cx_of(p) * ux + cy_of(p) * uy + cz_of(p) * uz;
+        feq[p] = w_of<double>(p) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - usq);
+    });
+}
+
+// element p of a register array without dynamic indexing
+__device__ __forceinline__ double pick19(const double* a, int p) {
+    double v = 0.0;
+    for_pops([&](auto P) {
+        constexpr int k = decltype(P)::value;
+        v = (p == k) ? a[k] : v;
+    });
+    return v;
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_init(const Replica* __restrict__ reps, int r,
+                                              typename Codec<S>::T* __restrict__ dst,
+                                              const double* __restrict__ rho_in,
+                                              const double* __restrict__ u_in,
+                                              const double* __restrict__ pops_in) {
+    using C = Codec<S>;
+    const Replica& R = reps[r];
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= R.V) return;
+    const long long V = R.V;
+    const int sx = s % R.nx, sy = (s / R.nx) % R.ny, sz = s / (R.nx * R.ny);
+    const bool solid = is_solid(R, sx, sy, sz);
+    typename C::T* out = dst + R.pop_base + s;
+    for_pops([&](auto P) {
+        constexpr int q = decltype(P)::value;
+        double val = w_of<double>(q) * R.rho0;
+        if (!solid) {
+            int p;
+            const int x = push_target<q>(R, sx, sy, sz, &p);
+            if (pops_in) {
+                val = pops_in[(long long)p * V + x];
+            } else {
+                const double rho = rho_in ? rho_in[x] : R.rho0;
+                double feq[Q];
+                if (u_in) feq19(rho, u_in[x], u_in[V + x], u_in[2 * V + x], feq);
+                else feq19(rho, 0.0, 0.0, 0.0, feq);
+                val = pick19(feq, p);
+            }
+        }
+        if constexpr (C::deviation) val -= w_of<double>(q) * R.rho0;
+        out[(long long)q * V] = C::template store<q>((typename C::R)val);
+    });
+}
+
+// ---------------------------------------------------------------------------------
+// Pre-collision view of the current state (lb_moments): pull-gather of one node,
+// decoded to FP64 full populations.
+// ---------------------------------------------------------------------------------
+template <int S>
+__device__ __forceinline__ void gather_f64(const Replica& R, const typename Codec<S>::T* __restrict__ src,
+                                           int x, int y, int z, double* f) {
+    using C = Codec<S>;
+    const long long V = R.V;
+    for_pops([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        int q;
+        const int node = pull_source<p>(R, x, y, z, &q);
+        double v = (double)C::template load<p>(src[R.pop_base + (long long)q * V + node]);
+        if constexpr (C::deviation) v += w_of<double>(p) * R.rho0;
+        f[p] = v;
+    });
+}
+
+// mode 0: populations [19][count]; mode 1: rho, u_x, u_y, u_z [4][count]
+template <int S>
+__global__ __launch_bounds__(256) void k_gather(const Replica* __restrict__ reps, int r,
+                                                const typename Codec<S>::T* __restrict__ src, int mode,
+                                                long long node0, int count, double* __restrict__ out) {
+    const Replica& R = reps[r];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    const long long s = node0 + i;
+    const int x = (int)(s % R.nx), y = (int)((s / R.nx) % R.ny), z = (int)(s / ((long long)R.nx * R.ny));
+    double f[Q];
+    if (is_solid(R, x, y, z)) {
+        for_pops([&](auto P) { f[decltype(P)::value] = 0.0; });
+    } else {
+        gather_f64<S>(R, src, x, y, z, f);
+    }
+    if (mode == 0) {
+        for_pops([&](auto P) {
+            constexpr int p = decltype(P)::value;
+            out[(long long)p * count + i] = f[p];
+        });
+    } else {
+        double rho = 0, jx = 0, jy = 0, jz = 0;
+        for_pops([&](auto P) {
+            constexpr int p = decltype(P)::value;
+            rho += f[p];
+            jx += cx_of(p) * f[p];
+            jy += cy_of(p) * f[p];
+            jz += cz_of(p) * f[p];
+        });
+        const double inv = rho != 0.0 ? 1.0 / rho : 0.0;
+        out[i] = rho;
+        out[count + i] = jx * inv;
+        out[2LL * count + i] = jy * inv;
+        out[3LL * count + i] = jz * inv;
+    }
+}
+
+// FP64 totals of rho and j over the fluid nodes of replica r: per-thread sums over
+// a fixed grid-stride, wavefront butterfly, block tree, one partial per block; a
+// second single-block pass adds the partials in a fixed order (deterministic).
+template <int S>
+__global__ __launch_bounds__(256) void k_conserved_partial(const Replica* __restrict__ reps, int r,
+                                                           const typename Codec<S>::T* __restrict__ src,
+                                                           double* __restrict__ partials) {
+    const Replica& R = reps[r];
+    double acc[4] = {0, 0, 0, 0};
+    for (int s = blockIdx.x * 256 + threadIdx.x; s < R.V; s += gridDim.x * 256) {
+        const int x = s % R.nx, y = (s / R.nx) % R.ny, z = s / (R.nx * R.ny);
+        if (is_solid(R, x, y, z)) continue;
+        double f[Q];
+        gather_f64<S>(R, src, x, y, z, f);
+        for_pops([&](auto P) {
+            constexpr int p = decltype(P)::value;
+            acc[0] += f[p];
+            acc[1] += cx_of(p) * f[p];
+            acc[2] += cy_of(p) * f[p];
+            acc[3] += cz_of(p) * f[p];
+        });
+    }
+    __shared__ double red[4][256 / 64];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double v = acc[k];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if ((threadIdx.x & 63) == 0) red[k][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double v = 0;
+        for (int w = 0; w < 256 / 64; ++w) v += red[threadIdx.x][w];
+        partials[blockIdx.x * 4 + threadIdx.x] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_conserved_final(const double* __restrict__ partials, int nblk,
+                                                         double* __restrict__ out4) {
+    __shared__ double red[4][256];
+    double acc[4] = {0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblk; b += 256)
+        for (int k = 0; k < 4; ++k) acc[k] += partials[b * 4 + k];
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int half = 128; half >= 1; half >>= 1) {
+        if (threadIdx.x < half)
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + half];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out4[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// ---------------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------------
+template <int S, int BLOCK>
+static hipError_t launch_sc_t(const Context& c, const void* src, void* dst, bool bump, hipStream_t s) {
+    using T = typename Codec<S>::T;
+    hipLaunchKernelGGL((k_stream_collide<S, BLOCK>), dim3(c.lat.total_tiles), dim3(BLOCK), 0, s,
+                       c.d_reps, c.lat.d_prefix, (int)c.reps.size(), (const T*)src, (T*)dst, c.d_state,
+                       bump ? 1 : 0);
+    return hipGetLastError();
+}
+
+template <int S>
+static hipError_t launch_sc_s(const Context& c, const void* src, void* dst, bool bump, hipStream_t s) {
+    switch (c.lat.block) {
+        case 64: return launch_sc_t<S, 64>(c, src, dst, bump, s);
+        case 128: return launch_sc_t<S, 128>(c, src, dst, bump, s);
+        case 256: return launch_sc_t<S, 256>(c, src, dst, bump, s);
+        case 512: return launch_sc_t<S, 512>(c, src, dst, bump, s);
+        case 1024: return launch_sc_t<S, 1024>(c, src, dst, bump, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_stream_collide(const Context& c, const void* src, void* dst, bool bump, hipStream_t s) {
+    switch (c.storage) {
+        case LB_STORE_F64: return launch_sc_s<LB_STORE_F64>(c, src, dst, bump, s);
+        case LB_STORE_F32: return launch_sc_s<LB_STORE_F32>(c, src, dst, bump, s);
+        case LB_STORE_F16DEV: return launch_sc_s<LB_STORE_F16DEV>(c, src, dst, bump, s);
+        case LB_STORE_BF16DEV: return launch_sc_s<LB_STORE_BF16DEV>(c, src, dst, bump, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int S>
+static hipError_t launch_init_t(const Context& c, int r, void* dst, const double* rho, const double* u,
+                                const double* pops, hipStream_t s) {
+    using T = typename Codec<S>::T;
+    const int V = c.reps[r].V;
+    hipLaunchKernelGGL((k_init<S>), dim3((V + 255) / 256), dim3(256), 0, s, c.d_reps, r, (T*)dst, rho, u,
+                       pops);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const Context& c, int r, void* dst, const double* rho, const double* u,
+                       const double* pops, hipStream_t s) {
+    switch (c.storage) {
+        case LB_STORE_F64: return launch_init_t<LB_STORE_F64>(c, r, dst, rho, u, pops, s);
+        case LB_STORE_F32: return launch_init_t<LB_STORE_F32>(c, r, dst, rho, u, pops, s);
+        case LB_STORE_F16DEV: return launch_init_t<LB_STORE_F16DEV>(c, r, dst, rho, u, pops, s);
+        case LB_STORE_BF16DEV: return launch_init_t<LB_STORE_BF16DEV>(c, r, dst, rho, u, pops, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int S>
+static hipError_t launch_gather_t(const Context& c, int r, const void* src, int mode, long long node0,
+                                  int count, double* out, hipStream_t s) {
+    using T = typename Codec<S>::T;
+    hipLaunchKernelGGL((k_gather<S>), dim3((count + 255) / 256), dim3(256), 0, s, c.d_reps, r,
+                       (const T*)src, mode, node0, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const Context& c, int r, const void* src, int mode, long long node0, int count,
+                         double* out, hipStream_t s) {
+    switch (c.storage) {
+        case LB_STORE_F64: return launch_gather_t<LB_STORE_F64>(c, r, src, mode, node0, count, out, s);
+        case LB_STORE_F32: return launch_gather_t<LB_STORE_F32>(c, r, src, mode, node0, count, out, s);
+        case LB_STORE_F16DEV: return launch_gather_t<LB_STORE_F16DEV>(c, r, src, mode, node0, count, out, s);
+        case LB_STORE_BF16DEV: return launch_gather_t<LB_STORE_BF16DEV>(c, r, src, mode, node0, count, out, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int S>
+static hipError_t launch_conserved_t(const Context& c, int r, const void* src, double* out4, hipStream_t s) {
+    using T = typename Codec<S>::T;
+    hipLaunchKernelGGL((k_conserved_partial<S>), dim3(c.partial_blocks), dim3(256), 0, s, c.d_reps, r,
+                       (const T*)src, c.d_partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_conserved_final, dim3(1), dim3(256), 0, s, (const double*)c.d_partials,
+                       c.partial_blocks, out4);
+    return hipGetLastError();
+}
+
+hipError_t launch_conserved(const Context& c, int r, const void* src, double* out4, hipStream_t s) {
+    switch (c.storage) {
+        case LB_STORE_F64: return launch_conserved_t<LB_STORE_F64>(c, r, src, out4, s);
+        case LB_STORE_F32: return launch_conserved_t<LB_STORE_F32>(c, r, src, out4, s);
+        case LB_STORE_F16DEV: return launch_conserved_t<LB_STORE_F16DEV>(c, r, src, out4, s);
+        case LB_STORE_BF16DEV: return launch_conserved_t<LB_STORE_BF16DEV>(c, r, src, out4, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace lbmd

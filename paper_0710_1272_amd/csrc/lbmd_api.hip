@@ -1,0 +1,773 @@
+// lbmd_api.hip -- the C ABI of lbmd.h: validation, buffers, step sequencing, observables.
+//
+// One coupled LB step (arXiv:0710.1272 Sec. II, steps 1-4) is enqueued as
+//   fork:  side stream  -> k_md (interpolate u_i, M substeps, Fbar, N_T/COM, node sums)
+//          main stream  -> k_stream_collide (current -> other buffer)
+//   join:  main stream  -> k_spread (S_p into the other buffer), step counter += 1
+// The lattice update does not need the beads (S_p is added after collision), so
+// the latency-bound MD of one workgroup per replica runs under the bandwidth-bound
+// lattice sweep.  The steps are captured once per buffer parity into HIP graphs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbmd_internal.hpp"
+
+using namespace lbmd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(e_ == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE,                  \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t store_size(int storage) {
+    switch (storage) {
+        case LB_STORE_F64: return 8;
+        case LB_STORE_F32: return 4;
+        case LB_STORE_F16DEV:
+        case LB_STORE_BF16DEV: return 2;
+        default: return 0;
+    }
+}
+
+size_t real_size(int storage) { return storage == LB_STORE_F64 ? 8 : 4; }
+
+const int kBlockSizes[] = {64, 128, 256, 512, 1024};
+const int kNumBlockSizes = 5;
+const long long kStageNodes = 1 << 20;
+
+struct Totals {
+    long long nodes = 0;
+    int beads = 0, max_beads = 0, max_V = 0;
+};
+
+Totals totals(const lbmd_config* cfg) {
+    Totals t;
+    for (int r = 0; r < cfg->n_replicas; ++r) {
+        const lbmd_replica& R = cfg->replicas[r];
+        const long long V = (long long)R.nx * R.ny * R.nz;
+        t.nodes += V;
+        t.max_V = std::max<long long>(t.max_V, V);
+        int nb = 0;
+        for (int c = 0; c < R.n_chains; ++c) nb += R.chain_len[c];
+        t.beads += nb;
+        t.max_beads = std::max(t.max_beads, nb);
+    }
+    return t;
+}
+
+}  // namespace
+
+namespace lbmd {
+
+WorkLayout work_layout(int n_reps, int max_V, long long max_stage_nodes) {
+    WorkLayout L{};
+    size_t off = 0;
+    L.reps = off;
+    off += align256(sizeof(Replica) * (size_t)n_reps);
+    L.state = off;
+    off += align256(sizeof(RunState));
+    L.partial_blocks = 1024;
+    L.partials = off;
+    off += align256(sizeof(double) * (4 * (size_t)L.partial_blocks + 4));
+    const long long stage_nodes = std::min<long long>(max_V, max_stage_nodes);
+    L.stage_doubles = (size_t)(19 * stage_nodes);
+    L.stage = off;
+    off += align256(sizeof(double) * L.stage_doubles);
+    L.n_prefix_tables = kNumBlockSizes;
+    L.prefix = off;
+    off += align256(sizeof(int) * (size_t)(n_reps + 1) * kNumBlockSizes);
+    L.total = off;
+    return L;
+}
+
+BeadLayout bead_layout(int ntot, int n_reps, size_t rs) {
+    BeadLayout L{};
+    size_t off = 0;
+    const size_t N = (size_t)std::max(ntot, 1);
+    L.r = off;        off += align256(3 * N * sizeof(double));
+    L.v = off;        off += align256(3 * N * rs);
+    L.u = off;        off += align256(3 * N * rs);
+    L.fbar = off;     off += align256(3 * N * rs);
+    L.node = off;     off += align256(N * sizeof(int));
+    L.bond_next = off; off += align256(N);
+    L.agg_node = off; off += align256(N * sizeof(int));
+    L.agg_f = off;    off += align256(3 * N * rs);
+    L.rep_of = off;   off += align256(N * sizeof(int));
+    L.diag = off;     off += align256(8 * (size_t)std::max(n_reps, 1) * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+}  // namespace lbmd
+
+struct lbmd_ctx {
+    Context c;
+};
+
+extern "C" {
+
+const char* lb_strerror(int code) {
+    switch (code) {
+        case LB_OK: return "success";
+        case LB_EINVAL: return "invalid argument or configuration";
+        case LB_ENOMEM: return "out of memory";
+        case LB_EDEVICE: return "HIP device or runtime error";
+        case LB_EUNSTABLE: return "device error word set (unstable or invalid state)";
+        case LB_ESTATE: return "call not valid in the current state";
+        case LB_ESIZE: return "output buffer too small";
+        default: return "unknown error code";
+    }
+}
+
+const char* lb_last_error_message(void) { return g_last_error.c_str(); }
+
+int lb_validate_config(const lbmd_config* cfg) {
+    if (!cfg) return fail(LB_EINVAL, "cfg is NULL");
+    if (cfg->n_replicas < 1 || !cfg->replicas) return fail(LB_EINVAL, "need n_replicas >= 1 and replicas");
+    if (!store_size(cfg->storage)) return fail(LB_EINVAL, "unknown storage");
+    if (cfg->block_size != 0) {
+        bool ok = false;
+        for (int b : kBlockSizes) ok = ok || b == cfg->block_size;
+        if (!ok) return fail(LB_EINVAL, "block_size must be 0, 64, 128, 256, 512 or 1024");
+    }
+    int total_beads = 0;
+    for (int r = 0; r < cfg->n_replicas; ++r) {
+        const lbmd_replica& R = cfg->replicas[r];
+        const std::string at = "replica " + std::to_string(r) + ": ";
+        if (R.nx < 2 || R.ny < 2 || R.nz < 2) return fail(LB_EINVAL, at + "box sides must be >= 2");
+        if ((long long)R.nx * R.ny * R.nz > (1LL << 30)) return fail(LB_EINVAL, at + "box above 2^30 nodes");
+        for (int a = 0; a < 3; ++a)
+            if (R.bc[a] != LB_BC_PERIODIC && R.bc[a] != LB_BC_FREESLIP)
+                return fail(LB_EINVAL, at + "unknown boundary type");
+        if (!(R.tau > 0.5) || !std::isfinite(R.tau)) return fail(LB_EINVAL, at + "tau must be > 1/2");
+        if (!(R.rho0 > 0.0) || !std::isfinite(R.rho0)) return fail(LB_EINVAL, at + "rho0 must be > 0");
+        if (R.n_walls < 0 || R.n_walls > LB_MAX_WALLS) return fail(LB_EINVAL, at + "n_walls out of range");
+        for (int k = 0; k < R.n_walls; ++k) {
+            const lbmd_wall& w = R.wall[k];
+            if (w.x0 > w.x1 || w.x0 < 2 || w.x1 > R.nx - 3)
+                return fail(LB_EINVAL, at + "wall planes must satisfy 2 <= x0 <= x1 <= nx-3");
+            if (w.y0 <= w.y1 || w.z0 <= w.z1) {
+                if (w.y0 > w.y1 || w.z0 > w.z1 || w.y0 < 0 || w.y1 >= R.ny || w.z0 < 0 || w.z1 >= R.nz)
+                    return fail(LB_EINVAL, at + "pore outside the cross-section");
+            }
+            if (k > 0 && w.x0 <= R.wall[k - 1].x1 + 2)
+                return fail(LB_EINVAL, at + "walls must be ordered along x and at least 2 planes apart");
+        }
+        if (R.n_chains < 0 || (R.n_chains > 0 && !R.chain_len))
+            return fail(LB_EINVAL, at + "chain_len missing");
+        int nb = 0;
+        for (int c = 0; c < R.n_chains; ++c) {
+            if (R.chain_len[c] < 1) return fail(LB_EINVAL, at + "chain lengths must be >= 1");
+            nb += R.chain_len[c];
+            if (nb > 4096) return fail(LB_EINVAL, at + "more than 4096 beads in one replica");
+        }
+        total_beads += nb;
+    }
+    const lbmd_md_params& m = cfg->md;
+    if (total_beads > 0) {
+        if (m.M < 1) return fail(LB_EINVAL, "md.M must be >= 1");
+        if (!(m.mass > 0) || !(m.gamma >= 0) || !(m.kT >= 0) || !(m.k_bond >= 0) || !(m.r0 > 0) ||
+            !(m.eps >= 0) || !(m.sigma > 0) || !(m.eps_w >= 0) || !(m.sigma_w > 0) ||
+            !std::isfinite(m.f_drive))
+            return fail(LB_EINVAL, "md parameters out of range");
+        if (m.drive_sign != 1 && m.drive_sign != -1) return fail(LB_EINVAL, "md.drive_sign must be +-1");
+        // kick-drift is stable for omega h < 2; the stiffest chain mode has omega = 2 sqrt(k/m)
+        if (2.0 * std::sqrt(m.k_bond / m.mass) / m.M >= 2.0)
+            return fail(LB_EINVAL, "bond stiffness unstable at this M: need 2 sqrt(k/m)/M < 2");
+        if (!cfg->init || !cfg->init->bead_r) return fail(LB_EINVAL, "beads need init->bead_r");
+    }
+    return LB_OK;
+}
+
+size_t lb_required_bytes(const lbmd_config* cfg, int which) {
+    if (lb_validate_config(cfg) != LB_OK) return 0;
+    const Totals t = totals(cfg);
+    switch (which) {
+        case LB_BUF_POPS: return align256((size_t)19 * (size_t)t.nodes * store_size(cfg->storage));
+        case LB_BUF_BEADS: return bead_layout(t.beads, cfg->n_replicas, real_size(cfg->storage)).total;
+        case LB_BUF_WORK: return work_layout(cfg->n_replicas, t.max_V, kStageNodes).total;
+        default: g_last_error = "unknown buffer id"; return 0;
+    }
+}
+
+}  // extern "C"
+
+namespace {
+
+int set_lattice_shape(Context& c, int block) {
+    for (auto& L : c.lat_all)
+        if (L.block == block) {
+            c.lat = L;
+            return LB_OK;
+        }
+    return fail(LB_EINVAL, "no launch table for block size");
+}
+
+template <class Real>
+int setup_beads(Context& c, const lbmd_config* cfg) {
+    const BeadLayout L = bead_layout(c.ntot_beads, (int)c.reps.size(), sizeof(Real));
+    char* base = (char*)c.beads;
+    BeadPtrs<Real>* p = new (std::nothrow) BeadPtrs<Real>;
+    if (!p) return fail(LB_ENOMEM, "host allocation");
+    p->r = (double*)(base + L.r);
+    p->v = (Real*)(base + L.v);
+    p->u = (Real*)(base + L.u);
+    p->fbar = (Real*)(base + L.fbar);
+    p->node = (int*)(base + L.node);
+    p->bond_next = (unsigned char*)(base + L.bond_next);
+    p->agg_node = (int*)(base + L.agg_node);
+    p->agg_f = (Real*)(base + L.agg_f);
+    p->rep_of = (int*)(base + L.rep_of);
+    p->diag = (double*)(base + L.diag);
+    p->ntot = c.ntot_beads;
+    c.bead_ptrs = p;
+
+    const int N = c.ntot_beads;
+    const size_t nz = (size_t)std::max(N, 1);
+    std::vector<double> r(3 * nz, 0.0);
+    std::vector<Real> v(3 * nz, Real(0));
+    std::vector<unsigned char> bn(nz, 0);
+    std::vector<int> rep_of(nz, 0), minus1(nz, -1);
+    std::vector<double> diag(8 * std::max<size_t>(c.reps.size(), 1), 0.0);
+    const lbmd_initial_state* in = cfg->init;
+    int g = 0;
+    for (size_t ri = 0; ri < c.reps.size(); ++ri) {
+        const lbmd_replica& R = cfg->replicas[ri];
+        for (int ch = 0; ch < R.n_chains; ++ch) {
+            for (int k = 0; k < R.chain_len[ch]; ++k, ++g) {
+                for (int a = 0; a < 3; ++a) {
+                    r[a * nz + g] = in->bead_r[3 * g + a];
+                    v[a * nz + g] = in->bead_v ? (Real)in->bead_v[3 * g + a] : Real(0);
+                }
+                bn[g] = k + 1 < R.chain_len[ch] ? 1 : 0;
+                rep_of[g] = (int)ri;
+            }
+        }
+        diag[8 * ri + 1] = -1.0;  // no completion yet
+    }
+    // SoA blocks are sized by ntot; when N == 0 nothing is copied
+    if (N > 0) {
+        for (int a = 0; a < 3; ++a) {
+            HIP_TRY(hipMemcpy(p->r + (size_t)a * N, r.data() + a * nz, N * sizeof(double), hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(p->v + (size_t)a * N, v.data() + a * nz, N * sizeof(Real), hipMemcpyHostToDevice));
+        }
+        HIP_TRY(hipMemset(p->u, 0, 3 * (size_t)N * sizeof(Real)));
+        HIP_TRY(hipMemset(p->fbar, 0, 3 * (size_t)N * sizeof(Real)));
+        HIP_TRY(hipMemset(p->agg_f, 0, 3 * (size_t)N * sizeof(Real)));
+        HIP_TRY(hipMemcpy(p->node, minus1.data(), N * sizeof(int), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(p->agg_node, minus1.data(), N * sizeof(int), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(p->bond_next, bn.data(), N, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(p->rep_of, rep_of.data(), N * sizeof(int), hipMemcpyHostToDevice));
+    }
+    HIP_TRY(hipMemcpy(p->diag, diag.data(), 8 * c.reps.size() * sizeof(double), hipMemcpyHostToDevice));
+    return LB_OK;
+}
+
+int init_populations(Context& c, const lbmd_config* cfg) {
+    const lbmd_initial_state* in = cfg->init;
+    long long node_off = 0;
+    double* d_tmp = nullptr;
+    size_t tmp_bytes = 0;
+    for (size_t r = 0; r < c.reps.size(); ++r) {
+        const long long V = c.reps[r].V;
+        const double *d_rho = nullptr, *d_u = nullptr, *d_pops = nullptr;
+        size_t need = 0;
+        if (in && in->pops) need = 19 * V;
+        else if (in && (in->rho || in->u)) need = 4 * V;
+        if (need * sizeof(double) > tmp_bytes) {
+            if (d_tmp) (void)hipFree(d_tmp);
+            d_tmp = nullptr;
+            tmp_bytes = need * sizeof(double);
+            hipError_t e = hipMalloc(&d_tmp, tmp_bytes);
+            if (e != hipSuccess) return fail(LB_ENOMEM, "staging for initial state");
+        }
+        if (in && in->pops) {
+            HIP_TRY(hipMemcpy(d_tmp, in->pops + 19 * node_off, 19 * V * sizeof(double), hipMemcpyHostToDevice));
+            d_pops = d_tmp;
+        } else if (in && (in->rho || in->u)) {
+            if (in->rho) {
+                HIP_TRY(hipMemcpy(d_tmp, in->rho + node_off, V * sizeof(double), hipMemcpyHostToDevice));
+                d_rho = d_tmp;
+            }
+            if (in->u) {
+                HIP_TRY(hipMemcpy(d_tmp + V, in->u + 3 * node_off, 3 * V * sizeof(double), hipMemcpyHostToDevice));
+                d_u = d_tmp + V;
+            }
+        }
+        HIP_TRY(launch_init(c, (int)r, c.pops[c.cur], d_rho, d_u, d_pops, c.stream));
+        HIP_TRY(hipStreamSynchronize(c.stream));
+        node_off += V;
+    }
+    if (d_tmp) HIP_TRY(hipFree(d_tmp));
+    return LB_OK;
+}
+
+int autotune(Context& c) {
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_block = c.lat.block;
+    for (int b : {128, 256, 512, 1024}) {
+        int rc = set_lattice_shape(c, b);
+        if (rc != LB_OK) return rc;
+        HIP_TRY(launch_stream_collide(c, c.pops[c.cur], c.pops[1 - c.cur], false, c.stream));
+        HIP_TRY(hipEventRecord(e0, c.stream));
+        for (int k = 0; k < 5; ++k)
+            HIP_TRY(launch_stream_collide(c, c.pops[c.cur], c.pops[1 - c.cur], false, c.stream));
+        HIP_TRY(hipEventRecord(e1, c.stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            best_block = b;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return set_lattice_shape(c, best_block);
+}
+
+void destroy_graphs(Context& c) {
+    for (int k = 0; k < 2; ++k) {
+        if (c.graph_coupled[k]) (void)hipGraphExecDestroy(c.graph_coupled[k]);
+        if (c.graph_lb[k]) (void)hipGraphExecDestroy(c.graph_lb[k]);
+        c.graph_coupled[k] = c.graph_lb[k] = nullptr;
+    }
+}
+
+void release(Context& c) {
+    destroy_graphs(c);
+    if (c.side) (void)hipStreamDestroy(c.side);
+    if (c.cap) (void)hipStreamDestroy(c.cap);
+    if (c.ev_fork) (void)hipEventDestroy(c.ev_fork);
+    if (c.ev_join) (void)hipEventDestroy(c.ev_join);
+    if (c.owns_buffers) {
+        for (int k = 0; k < 2; ++k)
+            if (c.pops[k]) (void)hipFree(c.pops[k]);
+        if (c.beads) (void)hipFree(c.beads);
+        if (c.work) (void)hipFree(c.work);
+    }
+    if (c.bead_ptrs) {
+        if (c.storage == LB_STORE_F64) delete (BeadPtrs<double>*)c.bead_ptrs;
+        else delete (BeadPtrs<float>*)c.bead_ptrs;
+    }
+    c.bead_ptrs = nullptr;
+}
+
+// enqueue one LB step on the context's streams (no graph)
+hipError_t enqueue_step(Context& c, bool coupled, int cur, hipStream_t main) {
+    void* src = c.pops[cur];
+    void* dst = c.pops[1 - cur];
+    if (coupled && c.ntot_beads > 0) {
+        hipError_t e;
+        if ((e = hipEventRecord(c.ev_fork, main)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(c.side, c.ev_fork, 0)) != hipSuccess) return e;
+        if ((e = launch_md(c, src, MD_COUPLED, c.side)) != hipSuccess) return e;
+        if ((e = hipEventRecord(c.ev_join, c.side)) != hipSuccess) return e;
+        if ((e = launch_stream_collide(c, src, dst, false, main)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(main, c.ev_join, 0)) != hipSuccess) return e;
+        return launch_spread(c, dst, true, main);
+    }
+    return launch_stream_collide(c, src, dst, true, main);
+}
+
+int build_graph(Context& c, bool coupled, int parity, hipGraphExec_t* out) {
+    hipGraph_t g = nullptr;
+    // the caller's stream may be the null stream, which cannot be captured: capture on
+    // a private stream; the instantiated graph is then launched on the caller's stream
+    HIP_TRY(hipStreamBeginCapture(c.cap, hipStreamCaptureModeThreadLocal));
+    int cur = parity;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < c.graph_unroll && e == hipSuccess; ++k) {
+        e = enqueue_step(c, coupled, cur, c.cap);
+        cur = 1 - cur;
+    }
+    hipError_t e2 = hipStreamEndCapture(c.cap, &g);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(LB_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    if (e2 != hipSuccess) return fail(LB_EDEVICE, std::string("end capture: ") + hipGetErrorString(e2));
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(LB_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, lbmd_ctx** out) {
+    if (!out) return fail(LB_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = lb_validate_config(cfg);
+    if (rc != LB_OK) return rc;
+    if (bufs && (!bufs->pops[0] || !bufs->pops[1] || !bufs->beads || !bufs->work))
+        return fail(LB_EINVAL, "caller buffers: all four pointers are required");
+
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(LB_EDEVICE, std::string("device is ") + prop.gcnArchName + ", library is built for gfx950");
+
+    lbmd_ctx* ctx = new (std::nothrow) lbmd_ctx;
+    if (!ctx) return fail(LB_ENOMEM, "host allocation");
+    Context& c = ctx->c;
+    c.cfg = *cfg;
+    c.storage = cfg->storage;
+    c.md_params = cfg->md;
+    c.stream = (hipStream_t)hip_stream;
+    c.use_graph = !(cfg->flags & LB_CFG_NO_GRAPH);
+
+    const Totals t = totals(cfg);
+    c.total_nodes = t.nodes;
+    c.pop_elems = 19 * t.nodes;
+    c.ntot_beads = t.beads;
+    c.max_beads = t.max_beads;
+    c.max_V = t.max_V;
+
+    // replica descriptors
+    long long pop_base = 0;
+    int bead0 = 0;
+    for (int r = 0; r < cfg->n_replicas; ++r) {
+        const lbmd_replica& in = cfg->replicas[r];
+        Replica R{};
+        R.nx = in.nx;
+        R.ny = in.ny;
+        R.nz = in.nz;
+        R.V = in.nx * in.ny * in.nz;
+        for (int a = 0; a < 3; ++a) R.fs[a] = in.bc[a] == LB_BC_FREESLIP ? 1 : 0;
+        R.n_walls = in.n_walls;
+        R.wzone_lo = 1 << 30;
+        R.wzone_hi = -1;
+        for (int k = 0; k < in.n_walls; ++k) {
+            const lbmd_wall& w = in.wall[k];
+            const int v6[6] = {w.x0, w.x1, w.y0, w.y1, w.z0, w.z1};
+            for (int m = 0; m < 6; ++m) R.wall[k][m] = v6[m];
+            R.wzone_lo = std::min(R.wzone_lo, w.x0 - 1);
+            R.wzone_hi = std::max(R.wzone_hi, w.x1 + 1);
+        }
+        R.pop_base = pop_base;
+        pop_base += 19LL * R.V;
+        int nb = 0;
+        for (int ch = 0; ch < in.n_chains; ++ch) nb += in.chain_len[ch];
+        R.bead0 = bead0;
+        R.n_beads = nb;
+        bead0 += nb;
+        R.seed_lo = (uint32_t)(in.seed & 0xFFFFFFFFu);
+        R.seed_hi = (uint32_t)(in.seed >> 32);
+        R.omega = 1.0 / in.tau;
+        R.rho0 = in.rho0;
+        R.xmid = in.n_walls > 0 ? 0.5 * (in.wall[0].x0 + in.wall[0].x1) : 0.5 * (in.nx - 1);
+        R.div_nx = make_fastdiv((uint32_t)in.nx);
+        R.div_ny = make_fastdiv((uint32_t)in.ny);
+        c.reps.push_back(R);
+    }
+
+    // bead-model constants
+    const lbmd_md_params& m = cfg->md;
+    MDDev& md = c.md;
+    md.M = std::max(m.M, 1);
+    md.h = 1.0 / md.M;
+    md.inv_M = 1.0 / md.M;
+    md.mass = m.mass;
+    md.inv_mass = m.mass > 0 ? 1.0 / m.mass : 0.0;
+    md.gamma = m.gamma;
+    md.A = std::sqrt(24.0 * m.mass * m.gamma * m.kT / md.h);
+    md.k_bond = m.k_bond;
+    md.r0 = m.r0;
+    md.eps = m.eps;
+    md.sigma2 = m.sigma * m.sigma;
+    md.rc2 = std::pow(2.0, 1.0 / 3.0) * md.sigma2;
+    md.eps_w = m.eps_w;
+    md.sigma_w2 = m.sigma_w * m.sigma_w;
+    md.rcw2 = std::pow(2.0, 1.0 / 3.0) * md.sigma_w2;
+    md.f_drive = m.drive_sign * m.f_drive;
+
+    // buffers
+    const size_t pop_bytes = lb_required_bytes(cfg, LB_BUF_POPS);
+    const size_t bead_bytes = lb_required_bytes(cfg, LB_BUF_BEADS);
+    const size_t work_bytes = lb_required_bytes(cfg, LB_BUF_WORK);
+    auto bail = [&](int code) {
+        release(c);
+        delete ctx;
+        return code;
+    };
+    if (bufs) {
+        c.pops[0] = bufs->pops[0];
+        c.pops[1] = bufs->pops[1];
+        c.beads = bufs->beads;
+        c.work = bufs->work;
+        c.owns_buffers = false;
+    } else {
+        c.owns_buffers = true;
+        if (hipMalloc(&c.pops[0], pop_bytes) != hipSuccess || hipMalloc(&c.pops[1], pop_bytes) != hipSuccess ||
+            hipMalloc(&c.beads, bead_bytes) != hipSuccess || hipMalloc(&c.work, work_bytes) != hipSuccess)
+            return bail(fail(LB_ENOMEM, "device allocation of " + std::to_string(2 * pop_bytes + bead_bytes + work_bytes) + " bytes"));
+    }
+    for (void* p : {c.pops[0], c.pops[1], c.beads, c.work})
+        if (((uintptr_t)p & 255) != 0) return bail(fail(LB_EINVAL, "buffers must be 256-byte aligned"));
+
+    const WorkLayout W = work_layout((int)c.reps.size(), c.max_V, kStageNodes);
+    char* wb = (char*)c.work;
+    c.d_reps = (Replica*)(wb + W.reps);
+    c.d_state = (RunState*)(wb + W.state);
+    c.d_partials = (double*)(wb + W.partials);
+    c.partial_blocks = W.partial_blocks;
+    c.d_stage = (double*)(wb + W.stage);
+    c.stage_doubles = W.stage_doubles;
+
+    auto check = [&](hipError_t e, const char* what) -> int {
+        if (e == hipSuccess) return LB_OK;
+        return fail(e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    if ((rc = check(hipMemcpy(c.d_reps, c.reps.data(), sizeof(Replica) * c.reps.size(), hipMemcpyHostToDevice), "upload replicas")))
+        return bail(rc);
+    RunState st{};
+    st.step = cfg->init ? cfg->init->step0 : 0;
+    c.host_step = st.step;
+    if ((rc = check(hipMemcpy(c.d_state, &st, sizeof st, hipMemcpyHostToDevice), "upload state"))) return bail(rc);
+
+    // tile prefix tables for every lattice block size
+    int* prefix_base = (int*)(wb + W.prefix);
+    for (int bi = 0; bi < kNumBlockSizes; ++bi) {
+        const int b = kBlockSizes[bi];
+        std::vector<int> pre(c.reps.size() + 1, 0);
+        for (size_t r = 0; r < c.reps.size(); ++r) pre[r + 1] = pre[r] + (c.reps[r].V + b - 1) / b;
+        LatticeLaunch L;
+        L.block = b;
+        L.total_tiles = pre.back();
+        L.d_prefix = prefix_base + bi * (int)(c.reps.size() + 1);
+        if ((rc = check(hipMemcpy(L.d_prefix, pre.data(), sizeof(int) * pre.size(), hipMemcpyHostToDevice), "upload tiles")))
+            return bail(rc);
+        c.lat_all.push_back(L);
+    }
+    if ((rc = set_lattice_shape(c, cfg->block_size ? cfg->block_size : 256))) return bail(rc);
+
+    if ((rc = check(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking), "side stream"))) return bail(rc);
+    if ((rc = check(hipStreamCreateWithFlags(&c.cap, hipStreamNonBlocking), "capture stream"))) return bail(rc);
+    if ((rc = check(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming), "event"))) return bail(rc);
+    if ((rc = check(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming), "event"))) return bail(rc);
+
+    rc = c.storage == LB_STORE_F64 ? setup_beads<double>(c, cfg) : setup_beads<float>(c, cfg);
+    if (rc) return bail(rc);
+    c.cur = 0;
+    if ((rc = init_populations(c, cfg))) return bail(rc);
+    if (c.ntot_beads > 0) {
+        // a mode-0 launch of the bead kernel changes nothing; it sets the kernel's
+        // LDS attribute here rather than inside a later graph capture
+        if ((rc = check(launch_md(c, c.pops[c.cur], 0, c.stream), "bead kernel warm-up"))) return bail(rc);
+    }
+    if (cfg->flags & LB_CFG_AUTOTUNE) {
+        if ((rc = autotune(c))) return bail(rc);
+    }
+    if ((rc = check(hipStreamSynchronize(c.stream), "sync"))) return bail(rc);
+    *out = ctx;
+    return LB_OK;
+}
+
+int lb_step(lbmd_ctx* ctx, int n_steps, unsigned flags) {
+    if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+    if (n_steps < 0) return fail(LB_EINVAL, "n_steps < 0");
+    Context& c = ctx->c;
+    const bool coupled = (flags & LB_STEP_COUPLED) != 0;
+    int done = 0;
+    if (c.use_graph && n_steps >= c.graph_unroll) {
+        hipGraphExec_t* slot = coupled ? c.graph_coupled : c.graph_lb;
+        while (n_steps - done >= c.graph_unroll) {
+            if (!slot[c.cur]) {
+                int rc = build_graph(c, coupled, c.cur, &slot[c.cur]);
+                if (rc) return rc;
+            }
+            HIP_TRY(hipGraphLaunch(slot[c.cur], c.stream));
+            if (c.graph_unroll & 1) c.cur = 1 - c.cur;
+            done += c.graph_unroll;
+        }
+    }
+    for (; done < n_steps; ++done) {
+        HIP_TRY(enqueue_step(c, coupled, c.cur, c.stream));
+        c.cur = 1 - c.cur;
+    }
+    c.host_step += n_steps;
+    return LB_OK;
+}
+
+int lb_couple(lbmd_ctx* ctx, unsigned dir) {
+    if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+    Context& c = ctx->c;
+    if (dir != LB_COUPLE_INTERP && dir != LB_COUPLE_SPREAD) return fail(LB_EINVAL, "unknown direction");
+    if (c.ntot_beads == 0) return LB_OK;
+    if (dir == LB_COUPLE_INTERP) HIP_TRY(launch_md(c, c.pops[c.cur], MD_INTERP, c.stream));
+    else HIP_TRY(launch_spread(c, c.pops[c.cur], false, c.stream));
+    return LB_OK;
+}
+
+int md_step(lbmd_ctx* ctx) {
+    if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+    Context& c = ctx->c;
+    if (c.ntot_beads == 0) return LB_OK;
+    HIP_TRY(launch_md(c, c.pops[c.cur], MD_SUBSTEPS, c.stream));
+    return LB_OK;
+}
+
+size_t lb_moments_bytes(const lbmd_ctx* ctx, int replica, unsigned what) {
+    if (!ctx || replica < 0 || replica >= (int)ctx->c.reps.size()) return 0;
+    const Replica& R = ctx->c.reps[replica];
+    const size_t V = (size_t)R.V, n = (size_t)R.n_beads;
+    switch (what) {
+        case LB_MOM_CONSERVED: return 4 * sizeof(double);
+        case LB_MOM_FIELDS: return 4 * V * sizeof(double);
+        case LB_MOM_POPULATIONS: return 19 * V * sizeof(double);
+        case LB_MOM_BEADS: return 6 * n * sizeof(double);
+        case LB_MOM_TRANSLOC: return 6 * sizeof(double);
+        case LB_MOM_COUPLING: return 7 * n * sizeof(double);
+        case LB_MOM_STATUS: return 2 * sizeof(double);
+        default: return 0;
+    }
+}
+
+int lb_block_size(const lbmd_ctx* ctx) { return ctx ? ctx->c.lat.block : 0; }
+
+}  // extern "C"
+
+namespace {
+
+template <class Real>
+int copy_bead_field(Context& c, const Replica& R, const Real* dev, int ncomp, double* out) {
+    const int n = R.n_beads, N = c.ntot_beads;
+    std::vector<Real> tmp((size_t)n);
+    for (int a = 0; a < ncomp; ++a) {
+        HIP_TRY(hipMemcpyAsync(tmp.data(), dev + (size_t)a * N + R.bead0, n * sizeof(Real), hipMemcpyDeviceToHost, c.stream));
+        HIP_TRY(hipStreamSynchronize(c.stream));
+        for (int i = 0; i < n; ++i) out[(size_t)ncomp * i + a] = (double)tmp[i];
+    }
+    return LB_OK;
+}
+
+template <class Real>
+int moments_beads(Context& c, int replica, unsigned what, double* out) {
+    const BeadPtrs<Real>& b = *(const BeadPtrs<Real>*)c.bead_ptrs;
+    const Replica& R = c.reps[replica];
+    const int n = R.n_beads;
+    if (n == 0) return LB_OK;
+    int rc;
+    if (what == LB_MOM_BEADS) {
+        if ((rc = copy_bead_field<double>(c, R, b.r, 3, out))) return rc;
+        return copy_bead_field<Real>(c, R, b.v, 3, out + 3 * (size_t)n);
+    }
+    if ((rc = copy_bead_field<Real>(c, R, b.u, 3, out))) return rc;
+    if ((rc = copy_bead_field<Real>(c, R, b.fbar, 3, out + 3 * (size_t)n))) return rc;
+    std::vector<int> nd((size_t)n);
+    HIP_TRY(hipMemcpyAsync(nd.data(), b.node + R.bead0, n * sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    for (int i = 0; i < n; ++i) out[6 * (size_t)n + i] = nd[i];
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lb_moments(lbmd_ctx* ctx, int replica, unsigned what, void* host_out, size_t bytes) {
+    if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+    Context& c = ctx->c;
+    if (replica < 0 || replica >= (int)c.reps.size()) return fail(LB_EINVAL, "replica out of range");
+    const size_t need = lb_moments_bytes(ctx, replica, what);
+    if (!need) return fail(LB_EINVAL, "unknown observable");
+    if (!host_out || bytes < need) return fail(LB_ESIZE, "need " + std::to_string(need) + " bytes");
+    double* out = (double*)host_out;
+    const Replica& R = c.reps[replica];
+    const void* cur = c.pops[c.cur];
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    switch (what) {
+        case LB_MOM_CONSERVED: {
+            double* d_out4 = c.d_partials + 4 * (size_t)c.partial_blocks;
+            HIP_TRY(launch_conserved(c, replica, cur, d_out4, c.stream));
+            HIP_TRY(hipMemcpyAsync(out, d_out4, 4 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+            break;
+        }
+        case LB_MOM_FIELDS:
+        case LB_MOM_POPULATIONS: {
+            const int ncomp = what == LB_MOM_FIELDS ? 4 : 19;
+            const long long chunk = (long long)(c.stage_doubles / 19);
+            for (long long n0 = 0; n0 < R.V; n0 += chunk) {
+                const int cnt = (int)std::min<long long>(chunk, R.V - n0);
+                HIP_TRY(launch_gather(c, replica, cur, ncomp == 4 ? 1 : 0, n0, cnt, c.d_stage, c.stream));
+                for (int k = 0; k < ncomp; ++k)
+                    HIP_TRY(hipMemcpyAsync(out + (size_t)k * R.V + n0, c.d_stage + (size_t)k * cnt,
+                                           cnt * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+            }
+            break;
+        }
+        case LB_MOM_BEADS:
+        case LB_MOM_COUPLING: {
+            int rc = c.storage == LB_STORE_F64 ? moments_beads<double>(c, replica, what, out)
+                                               : moments_beads<float>(c, replica, what, out);
+            if (rc) return rc;
+            break;
+        }
+        case LB_MOM_TRANSLOC: {
+            const double* diag = c.storage == LB_STORE_F64 ? ((BeadPtrs<double>*)c.bead_ptrs)->diag
+                                                           : ((BeadPtrs<float>*)c.bead_ptrs)->diag;
+            double d[8];
+            HIP_TRY(hipMemcpyAsync(d, diag + 8 * replica, sizeof d, hipMemcpyDeviceToHost, c.stream));
+            HIP_TRY(hipStreamSynchronize(c.stream));
+            out[0] = d[0];
+            out[1] = d[1];
+            out[2] = d[2];
+            out[3] = d[3];
+            out[4] = d[4];
+            out[5] = (double)c.host_step;
+            break;
+        }
+        case LB_MOM_STATUS:
+            break;
+    }
+    RunState st;
+    HIP_TRY(hipMemcpyAsync(&st, c.d_state, sizeof st, hipMemcpyDeviceToHost, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    if (what == LB_MOM_STATUS) {
+        out[0] = (double)st.err;
+        out[1] = (double)st.step;
+    }
+    if (st.err) return fail(LB_EUNSTABLE, "device error word " + std::to_string(st.err));
+    return LB_OK;
+}
+
+int lb_destroy(lbmd_ctx* ctx) {
+    if (!ctx) return LB_OK;
+    Context& c = ctx->c;
+    (void)hipStreamSynchronize(c.stream);
+    release(c);
+    delete ctx;
+    return LB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,335 @@
+// lbmd_device.hpp -- device-side building blocks of the coupled LB / bead library (gfx950).
+//
+// Lattice: D3Q19 (arXiv:0710.1272 Sec. II, "the standard three-dimensional 19-speed
+// lattice"), weights 1/3, 1/18, 1/36, c_s^2 = 1/3, in the population order of lbmd.h.
+// Storage codecs: FP64, FP32, and 16-bit deviations h_p = s_p (f_p - w_p rho0) with
+// s_p = 2, 16, 32 (powers of two near 1/w_p, keeping FP16 away from subnormals).
+// Geometry is analytic (box size, face types, walls with a pore); no per-node flags.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbmd.h"
+
+namespace lbmd {
+
+constexpr int Q = 19;
+
+__host__ __device__ constexpr int cx_of(int p) {
+    constexpr int t[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    return t[p];
+}
+__host__ __device__ constexpr int cy_of(int p) {
+    constexpr int t[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    return t[p];
+}
+__host__ __device__ constexpr int cz_of(int p) {
+    constexpr int t[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    return t[p];
+}
+// population with velocity -c_p: pairs are (2k-1, 2k)
+__host__ __device__ constexpr int opp_of(int p) { return p == 0 ? 0 : ((p & 1) ? p + 1 : p - 1); }
+
+__host__ __device__ constexpr int find_pop(int x, int y, int z) {
+    for (int p = 0; p < Q; ++p)
+        if (cx_of(p) == x && cy_of(p) == y && cz_of(p) == z) return p;
+    return -1;
+}
+// population with component `axis` of c_p reversed (specular reflection)
+__host__ __device__ constexpr int mirror_of(int p, int axis) {
+    return axis == 0 ? find_pop(-cx_of(p), cy_of(p), cz_of(p))
+         : axis == 1 ? find_pop(cx_of(p), -cy_of(p), cz_of(p))
+                     : find_pop(cx_of(p), cy_of(p), -cz_of(p));
+}
+template <class R>
+__host__ __device__ constexpr R w_of(int p) {
+    return p == 0 ? R(1) / R(3) : (p <= 6 ? R(1) / R(18) : R(1) / R(36));
+}
+// 16-bit deviation scale (power of two)
+__host__ __device__ constexpr float scale_of(int p) { return p == 0 ? 2.0f : (p <= 6 ? 16.0f : 32.0f); }
+
+// ---------------------------------------------------------------------------------
+// Storage codecs.
+// ---------------------------------------------------------------------------------
+template <int S>
+struct Codec;
+
+template <>
+struct Codec<LB_STORE_F64> {
+    using T = double;
+    using R = double;
+    static constexpr bool deviation = false;
+    template <int P>
+    __device__ static R load(T v) { return v; }
+    template <int P>
+    __device__ static T store(R v) { return v; }
+};
+
+template <>
+struct Codec<LB_STORE_F32> {
+    using T = float;
+    using R = float;
+    static constexpr bool deviation = false;
+    template <int P>
+    __device__ static R load(T v) { return v; }
+    template <int P>
+    __device__ static T store(R v) { return v; }
+};
+
+template <>
+struct Codec<LB_STORE_F16DEV> {
+    using T = _Float16;
+    using R = float;
+    static constexpr bool deviation = true;
+    template <int P>
+    __device__ static R load(T v) { return (float)v * (1.0f / scale_of(P)); }
+    template <int P>
+    __device__ static T store(R v) { return (_Float16)(v * scale_of(P)); }  // IEEE round-to-nearest-even
+};
+
+template <>
+struct Codec<LB_STORE_BF16DEV> {
+    using T = uint16_t;
+    using R = float;
+    static constexpr bool deviation = true;
+    template <int P>
+    __device__ static R load(T v) {
+        return __builtin_bit_cast(float, (uint32_t)v << 16) * (1.0f / scale_of(P));
+    }
+    template <int P>
+    __device__ static T store(R v) {
+        // round to nearest even on the upper 16 bits; NaN kept quiet
+        uint32_t b = __builtin_bit_cast(uint32_t, v * scale_of(P));
+        if ((b & 0x7fffffffu) > 0x7f800000u) return (T)0x7fc0u;
+        b += 0x7fffu + ((b >> 16) & 1u);
+        return (T)(b >> 16);
+    }
+};
+
+// runtime-p wrappers (init / gather paths that are not performance critical)
+template <int S, int P = 0>
+__device__ inline typename Codec<S>::R load_rt(typename Codec<S>::T v, int p) {
+    if constexpr (P == Q) {
+        return 0;
+    } else {
+        if (p == P) return Codec<S>::template load<P>(v);
+        return load_rt<S, P + 1>(v, p);
+    }
+}
+template <int S, int P = 0>
+__device__ inline typename Codec<S>::T store_rt(typename Codec<S>::R v, int p) {
+    if constexpr (P == Q) {
+        return typename Codec<S>::T(0);
+    } else {
+        if (p == P) return Codec<S>::template store<P>(v);
+        return store_rt<S, P + 1>(v, p);
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Unsigned division by a run-time invariant (Granlund & Montgomery 1994, Fig. 4.1):
+// q = (t + ((n - t) >> 1)) >> (l - 1), t = mulhi(m, n), l = ceil(log2 d),
+// m = floor(2^32 (2^l - d) / d) + 1.  d = 1 is handled separately.
+// ---------------------------------------------------------------------------------
+struct FastDiv {
+    uint32_t d, m, s;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+    FastDiv f{d, 0u, 0u};
+    if (d <= 1) return f;
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    f.m = (uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1);
+    f.s = l;
+    return f;
+}
+__host__ __device__ inline uint32_t fdiv(uint32_t n, const FastDiv& f) {
+    if (f.d <= 1) return n;
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint32_t t = __umulhi(n, f.m);
+#else
+    uint32_t t = (uint32_t)(((uint64_t)n * f.m) >> 32);
+#endif
+    return (t + ((n - t) >> 1)) >> (f.s - 1);
+}
+
+// ---------------------------------------------------------------------------------
+// Replica descriptor: everything a kernel needs to know about one box.
+// ---------------------------------------------------------------------------------
+struct Replica {
+    int nx, ny, nz, V;
+    int fs[3];          // 1 if the axis has free-slip faces, 0 if periodic
+    int n_walls;
+    int wall[LB_MAX_WALLS][6];
+    int wzone_lo, wzone_hi;  // x range within one node of any wall (lanes that need solid checks)
+    long long pop_base; // element offset of this replica's [19][V] block
+    int bead0, n_beads;
+    uint32_t seed_lo, seed_hi;
+    double omega, rho0;
+    double xmid;        // mid-plane of wall 0, for the translocation count
+    FastDiv div_nx, div_ny;
+};
+
+__host__ __device__ inline bool pore_open(const int* w) { return w[2] <= w[3] && w[4] <= w[5]; }
+
+__host__ __device__ inline bool is_solid(const Replica& R, int x, int y, int z) {
+    bool s = false;
+    for (int k = 0; k < R.n_walls; ++k) {
+        const int* w = R.wall[k];
+        bool inx = x >= w[0] && x <= w[1];
+        bool pore = pore_open(w) && y >= w[2] && y <= w[3] && z >= w[4] && z <= w[5];
+        s = s || (inx && !pore);
+    }
+    return s;
+}
+
+__host__ __device__ inline bool is_pore(const Replica& R, int x, int y, int z) {
+    bool s = false;
+    for (int k = 0; k < R.n_walls; ++k) {
+        const int* w = R.wall[k];
+        s = s || (x >= w[0] && x <= w[1] && pore_open(w) && y >= w[2] && y <= w[3] && z >= w[4] &&
+                  z <= w[5]);
+    }
+    return s;
+}
+
+// population P with the components flagged in (fx, fy, fz) reversed; all
+// candidates are compile-time constants, the choice is a select tree
+template <int P>
+__host__ __device__ __forceinline__ int mirror_combo(bool fx, bool fy, bool fz) {
+    constexpr int mx = mirror_of(P, 0), my = mirror_of(P, 1), mz = mirror_of(P, 2);
+    constexpr int mxy = mirror_of(mx, 1), mxz = mirror_of(mx, 2), myz = mirror_of(my, 2);
+    constexpr int mxyz = mirror_of(mxy, 2);
+    return fx ? (fy ? (fz ? mxyz : mxy) : (fz ? mxz : mx)) : (fy ? (fz ? myz : my) : (fz ? mz : P));
+}
+
+// Pull resolver for a fluid node (x,y,z) and population P: where the value that
+// arrives in slot (x,P) was stored after the previous collision.  Source s = x - c_P;
+// a periodic axis wraps; a free-slip axis keeps x_a and reflects component a;
+// a solid source means the population bounced back: slot (x, opp(P)).
+// Returns the node index within the replica; *q receives the population.
+template <int P>
+__host__ __device__ __forceinline__ int pull_source(const Replica& R, int x, int y, int z, int* q) {
+    constexpr int cx = cx_of(P), cy = cy_of(P), cz = cz_of(P);
+    int sx = x - cx, sy = y - cy, sz = z - cz;
+    bool fx = false, fy = false, fz = false;
+    if constexpr (cx != 0) {
+        if (sx < 0 || sx >= R.nx) {
+            if (R.fs[0]) { sx = x; fx = true; }
+            else sx += sx < 0 ? R.nx : -R.nx;
+        }
+    }
+    if constexpr (cy != 0) {
+        if (sy < 0 || sy >= R.ny) {
+            if (R.fs[1]) { sy = y; fy = true; }
+            else sy += sy < 0 ? R.ny : -R.ny;
+        }
+    }
+    if constexpr (cz != 0) {
+        if (sz < 0 || sz >= R.nz) {
+            if (R.fs[2]) { sz = z; fz = true; }
+            else sz += sz < 0 ? R.nz : -R.nz;
+        }
+    }
+    int qq = mirror_combo<P>(fx, fy, fz);
+    if (is_solid(R, sx, sy, sz)) {
+        sx = x;
+        sy = y;
+        sz = z;
+        qq = opp_of(P);
+    }
+    *q = qq;
+    return sx + R.nx * (sy + R.ny * sz);
+}
+
+// Push resolver (inverse of pull_source): where population Q leaving fluid node s
+// ends up.  Used to build a post-collision buffer whose pull gives wanted populations.
+template <int QP>
+__host__ __device__ __forceinline__ int push_target(const Replica& R, int sx, int sy, int sz, int* p) {
+    constexpr int cx = cx_of(QP), cy = cy_of(QP), cz = cz_of(QP);
+    int tx = sx + cx, ty = sy + cy, tz = sz + cz;
+    bool fx = false, fy = false, fz = false;
+    if constexpr (cx != 0) {
+        if (tx < 0 || tx >= R.nx) {
+            if (R.fs[0]) { tx = sx; fx = true; }
+            else tx += tx < 0 ? R.nx : -R.nx;
+        }
+    }
+    if constexpr (cy != 0) {
+        if (ty < 0 || ty >= R.ny) {
+            if (R.fs[1]) { ty = sy; fy = true; }
+            else ty += ty < 0 ? R.ny : -R.ny;
+        }
+    }
+    if constexpr (cz != 0) {
+        if (tz < 0 || tz >= R.nz) {
+            if (R.fs[2]) { tz = sz; fz = true; }
+            else tz += tz < 0 ? R.nz : -R.nz;
+        }
+    }
+    int pp = mirror_combo<QP>(fx, fy, fz);
+    if (is_solid(R, tx, ty, tz)) {
+        tx = sx;
+        ty = sy;
+        tz = sz;
+        pp = opp_of(QP);
+    }
+    *p = pp;
+    return tx + R.nx * (ty + R.ny * tz);
+}
+
+// ---------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two 32x32->64
+// multiplies with a Weyl-sequence key schedule.
+// ---------------------------------------------------------------------------------
+struct U4 {
+    uint32_t x, y, z, w;
+};
+__host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        uint64_t a = (uint64_t)0xD2511F53u * c.x;
+        uint64_t b = (uint64_t)0xCD9E8D57u * c.z;
+        U4 n;
+        n.x = (uint32_t)(b >> 32) ^ c.y ^ k0;
+        n.y = (uint32_t)b;
+        n.z = (uint32_t)(a >> 32) ^ c.w ^ k1;
+        n.w = (uint32_t)a;
+        c = n;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+// top 24 bits as a signed fraction in [-1/2, 1/2); exact in FP32
+template <class R>
+__host__ __device__ inline R centred_uniform(uint32_t r) {
+    return (R)(int32_t)(r & 0xFFFFFF00u) * (R)(1.0 / 4294967296.0);
+}
+
+// ---------------------------------------------------------------------------------
+// Device-side run state and bead buffers.
+// ---------------------------------------------------------------------------------
+struct RunState {
+    long long step;  // LB step counter (Philox counter word)
+    unsigned err;    // error word, LB_ERR_* bits
+    unsigned pad;
+};
+
+template <class Real>
+struct BeadPtrs {
+    double* r;          // [3][Ntot] positions (FP64 accumulation)
+    Real* v;            // [3][Ntot]
+    Real* u;            // [3][Ntot] interpolated fluid velocity
+    Real* fbar;         // [3][Ntot] substep-averaged drag + random force
+    int* node;          // [Ntot] nearest node (within the replica), -1 on solid
+    unsigned char* bond_next;  // [Ntot] 1 if bead i and i+1 are bonded
+    int* agg_node;      // [Ntot] node of a bead that leads its node's sum, else -1
+    Real* agg_f;        // [3][Ntot] summed Fbar of the beads sharing agg_node
+    int* rep_of;        // [Ntot] replica of each bead
+    double* diag;       // [n_replicas][8]: N_T, t_done, com x,y,z, last step, -, -
+    int ntot;
+};
+
+}  // namespace lbmd

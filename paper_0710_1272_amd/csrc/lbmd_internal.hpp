@@ -1,0 +1,106 @@
+// lbmd_internal.hpp -- host-side internals shared by the kernels and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "lbmd.h"
+#include "lbmd_device.hpp"
+
+namespace lbmd {
+
+// Scalar bead-model parameters as the MD kernel uses them.
+struct MDDev {
+    int M;
+    double h, inv_M;
+    double mass, inv_mass, gamma, A;  // A = sqrt(24 m gamma kT / h)
+    double k_bond, r0;
+    double eps, sigma2, rc2;          // WCA bead-bead: rc^2 = 2^(1/3) sigma^2
+    double eps_w, sigma_w2, rcw2;     // WCA bead-surface
+    double f_drive;                   // signed along x
+};
+
+enum MDMode : int { MD_INTERP = 1, MD_SUBSTEPS = 2, MD_COUPLED = 3 };
+
+// Lattice-kernel launch description for one block size.
+struct LatticeLaunch {
+    int block = 0;
+    int total_tiles = 0;
+    int* d_prefix = nullptr;  // [n_reps + 1] first tile of each replica
+};
+
+struct Context {
+    lbmd_config cfg{};                 // copy; pointer members not kept
+    int storage = LB_STORE_F32;
+    std::vector<Replica> reps;         // host copies
+    std::vector<int> chain_len_all;
+    lbmd_md_params md_params{};
+    MDDev md{};
+    long long total_nodes = 0;         // sum of V over replicas
+    long long pop_elems = 0;           // 19 * total_nodes
+    int ntot_beads = 0;
+    int max_beads = 0;
+    int max_V = 0;
+
+    hipStream_t stream = nullptr;      // caller's stream
+    hipStream_t side = nullptr;        // MD branch of the coupled step
+    hipStream_t cap = nullptr;         // private stream used only to capture graphs
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
+    void* pops[2] = {nullptr, nullptr};
+    void* beads = nullptr;
+    void* work = nullptr;
+    bool owns_buffers = false;
+    int cur = 0;                       // which pops buffer holds the current state
+    long long host_step = 0;           // mirror of the device step counter
+
+    // carved from `work`
+    Replica* d_reps = nullptr;
+    RunState* d_state = nullptr;
+    double* d_partials = nullptr;      // reduction partials
+    double* d_stage = nullptr;         // lb_moments staging
+    size_t stage_doubles = 0;
+    int partial_blocks = 0;
+    void* bead_ptrs = nullptr;         // BeadPtrs<float> or BeadPtrs<double> (by storage)
+
+    LatticeLaunch lat;                 // current lattice launch shape
+    std::vector<LatticeLaunch> lat_all;
+    int md_block = 256;
+
+    bool use_graph = true;
+    hipGraphExec_t graph_coupled[2] = {nullptr, nullptr};  // by parity of cur
+    hipGraphExec_t graph_lb[2] = {nullptr, nullptr};
+    int graph_unroll = 8;
+};
+
+// work-buffer layout (byte offsets), computed on the host
+struct WorkLayout {
+    size_t reps, state, partials, stage, prefix, total;
+    size_t stage_doubles;
+    int partial_blocks;
+    int n_prefix_tables;
+};
+WorkLayout work_layout(int n_reps, int max_V, long long max_stage_nodes);
+
+// bead-buffer layout
+struct BeadLayout {
+    size_t r, v, u, fbar, node, bond_next, agg_node, agg_f, rep_of, diag, total;
+};
+BeadLayout bead_layout(int ntot, int n_reps, size_t real_size);
+
+// kernel launchers (lb_kernels.hip / md_kernels.hip); all enqueue on `s`
+hipError_t launch_stream_collide(const Context& c, const void* src, void* dst, bool bump_step,
+                                 hipStream_t s);
+hipError_t launch_init(const Context& c, int r, void* dst, const double* d_rho, const double* d_u,
+                       const double* d_pops, hipStream_t s);
+hipError_t launch_gather(const Context& c, int r, const void* src, int mode, long long node0,
+                         int count, double* out, hipStream_t s);
+hipError_t launch_conserved(const Context& c, int r, const void* src, double* d_out4, hipStream_t s);
+hipError_t launch_md(const Context& c, const void* cur, int mode, hipStream_t s);
+hipError_t launch_spread(const Context& c, void* dst, bool bump_step, hipStream_t s);
+hipError_t launch_bump(const Context& c, hipStream_t s);
+size_t md_lds_bytes(const Context& c);
+
+}  // namespace lbmd

@@ -1,0 +1,100 @@
+"""The C-ABI library loads, exports what include/lbmd.h declares, and validates
+configurations on the host (no device call is made by these functions)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_0710_1272_amd import lbmd as B
+from workloads import configs as WC
+from workloads.configs import FREESLIP, PERIODIC, Box, MDParams, Replica
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "lbmd.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(lb_\w+|md_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    names = _declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(names) == sorted(B.EXPORTED)
+
+
+def test_strerror():
+    L = B.lib()
+    assert L.lb_strerror(0) == b"success"
+    assert b"invalid" in L.lb_strerror(B.LB_EINVAL)
+    assert L.lb_strerror(-99) == b"unknown error code"
+
+
+def _cfg(replicas, md=None, storage=B.LB_STORE_F32, with_beads=True, **kw):
+    n = sum(r.n_beads for r in replicas)
+    init = {"bead_r": np.zeros((n, 3))} if (with_beads and n) else None
+    return B.Config(replicas, md or MDParams(), storage, init, **kw)
+
+
+@pytest.mark.parametrize("w", [WC.c1_shear_box(), WC.c2_translocation(), WC.c3_translocation(),
+                               WC.c4_batched(8), WC.c5_large()], ids=lambda w: w.name)
+def test_named_workloads_are_valid(w):
+    c = _cfg(w.replicas, w.md, w.storage)
+    assert c.validate() == B.LB_OK, B.lib().lb_last_error_message()
+    pops = c.required_bytes(B.LB_BUF_POPS)
+    elem = {0: 8, 1: 4, 2: 2, 3: 2}[w.storage]
+    assert pops >= 19 * w.nodes * elem
+    assert pops - 19 * w.nodes * elem < 256
+    assert c.required_bytes(B.LB_BUF_WORK) > 0 and c.required_bytes(B.LB_BUF_BEADS) > 0
+
+
+def _rep(**kw):
+    box = Box(**{**dict(nx=32, ny=16, nz=16, bc=(FREESLIP,) * 3, walls=((14, 16, 7, 9, 7, 9),)), **kw})
+    return Replica(box, [10], 1)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(tau=0.5), dict(tau=float("nan")), dict(rho0=0.0), dict(nx=1),
+    dict(walls=((1, 3, 7, 9, 7, 9),)), dict(walls=((14, 30, 7, 9, 7, 9),)),
+    dict(walls=((14, 16, 7, 16, 7, 9),)), dict(walls=((14, 16, 7, 9, 7, 9), (17, 18, 7, 9, 7, 9))),
+    dict(bc=(2, 0, 0)),
+])
+def test_invalid_boxes_rejected(bad):
+    c = _cfg([_rep(**bad)])
+    assert c.validate() == B.LB_EINVAL
+    assert c.required_bytes(B.LB_BUF_POPS) == 0
+    assert len(B.lib().lb_last_error_message()) > 0
+
+
+@pytest.mark.parametrize("bad", [dict(M=5), dict(M=0), dict(mass=0.0), dict(drive_sign=0),
+                                 dict(sigma=-1.0)])
+def test_invalid_md_rejected(bad):
+    md = MDParams(**bad)
+    assert _cfg([_rep()], md).validate() == B.LB_EINVAL
+
+
+def test_kick_drift_stability_limit():
+    # 2 sqrt(k/m)/M < 2: k = 100, m = 1 needs M > 10
+    assert _cfg([_rep()], MDParams(M=10)).validate() == B.LB_EINVAL
+    assert _cfg([_rep()], MDParams(M=11)).validate() == B.LB_OK
+
+
+def test_other_invalid_configs():
+    assert _cfg([_rep()], storage=7).validate() == B.LB_EINVAL
+    assert _cfg([_rep()], with_beads=False).validate() == B.LB_EINVAL  # beads need positions
+    assert _cfg([_rep()], block_size=96).validate() == B.LB_EINVAL
+    box = Box(8, 8, 8, (PERIODIC,) * 3)
+    assert _cfg([Replica(box, [], 0)], with_beads=False).validate() == B.LB_OK
+    assert _cfg([Replica(box, [5000], 0)]).validate() == B.LB_EINVAL
+
+
+def test_no_gpu_needed_for_host_calls():
+    # these calls must not touch the device: they work in a CPU-only process
+    c = _cfg([_rep()])
+    assert c.validate() == B.LB_OK
+    assert c.required_bytes(B.LB_BUF_POPS) == ((19 * 32 * 16 * 16 * 4 + 255) // 256) * 256

@@ -1,0 +1,282 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Tolerances: FP64 storage 1e-12 relative on populations; FP32 storage 1e-5 relative
+on populations after 100 steps; 16-bit storage 1e-3 of max|u| on the velocity field.
+Coupled runs also check the nearest-node decision margin along the trajectory
+against the GPU-oracle position drift, so that no rounding tie decides a node.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests.common import gpu_sim, log, max_rel, min_tie_distance, oracle_sim
+from workloads import configs as WC
+from workloads import generate as G
+from workloads.configs import FREESLIP, PERIODIC, Box, MDParams, Replica
+
+pytestmark = pytest.mark.gpu
+
+F64, F32, F16, BF16 = WC.STORE_F64, WC.STORE_F32, WC.STORE_F16, WC.STORE_BF16
+
+
+def _fluid(box):
+    return ~O.solid_mask(box)
+
+
+def test_c1_shear_wave_fp64():
+    w = WC.c1_shear_box()
+    rep = w.replicas[0]
+    box = rep.box
+    rho, u = G.shear_wave_fields(box, seed=rep.seed)
+    log("c1: shear wave 32^3 fp64, 100 steps")
+    ora = oracle_sim(rep, w.md, rho, u)
+    ora.step(100, coupled=False)
+    with gpu_sim([rep], w.md, F64, rho, u) as sim:
+        sim.step(100, coupled=False)
+        f = sim.populations()
+        cons = sim.conserved()
+    assert max_rel(f, ora.f, _fluid(box)) < 1e-12
+    c_ora = O.conserved(box, ora.f)
+    assert abs(cons[0] - c_ora[0]) < 1e-12 * c_ora[0]
+    assert np.allclose(cons[1:], c_ora[1:], rtol=0, atol=1e-12 * c_ora[0])
+    # shear wave decays at nu = (tau - 1/2)/3 (property at any size)
+    _, uu = O.fields(box, f)
+    x = np.arange(box.nodes) % box.nx
+    k = 2 * np.pi / box.nx
+    amp = 2.0 / box.nodes * np.sum(uu[1] * np.sin(k * x))
+    assert abs(amp / 0.01 - np.exp(-(1 / 6) * k * k * 100)) < 2e-3
+
+
+BOXES = [
+    Box(70, 12, 10, (FREESLIP,) * 3, ((30, 32, 4, 6, 3, 5),), 0.8),
+    Box(128, 8, 8, (PERIODIC, FREESLIP, FREESLIP), ((62, 64, 3, 5, 3, 5),), 1.0),
+    Box(96, 6, 6, (PERIODIC,) * 3, ((20, 21, 2, 3, 2, 3), (60, 62, 5, 4, 0, -1)), 0.7),
+    Box(6, 5, 7, (FREESLIP, PERIODIC, FREESLIP), ((2, 3, 1, 2, 3, 4),), 1.2),
+    Box(64, 4, 4, (FREESLIP, PERIODIC, PERIODIC), (), 0.9),
+]
+
+
+@pytest.mark.parametrize("block", [64, 256, 1024])
+@pytest.mark.parametrize("bi", range(len(BOXES)))
+def test_boundaries_fp64(bi, block):
+    box = BOXES[bi]
+    rep = Replica(box, [], 3)
+    rho, u = G.random_small_flow(box, seed=bi)
+    log(f"boundaries fp64 box={bi} block={block}")
+    ora = oracle_sim(rep, MDParams(), rho, u)
+    ora.step(30, coupled=False)
+    with gpu_sim([rep], MDParams(), F64, rho, u, block_size=block) as sim:
+        sim.step(30, coupled=False)
+        f = sim.populations()
+    assert max_rel(f, ora.f, _fluid(box)) < 1e-12
+
+
+def test_init_populations_roundtrip():
+    box = BOXES[0]
+    rep = Replica(box, [], 0)
+    rng = np.random.default_rng(4)
+    pops = O.equilibrium_populations(box, *G.random_small_flow(box, 1)) + 1e-3 * rng.random((19, box.nodes))
+    pops[:, O.solid_mask(box)] = 0.0
+    with gpu_sim([rep], MDParams(), F64, pops=pops) as sim:
+        f = sim.populations()
+    assert np.array_equal(f, pops)
+
+
+def test_c2_lb_only_fp32():
+    w = WC.c2_translocation(F32)
+    rep = w.replicas[0]
+    box = rep.box
+    rho, u = G.random_small_flow(box, seed=11, du=0.02)
+    log("c2 lb-only fp32, 100 steps")
+    ora = oracle_sim(rep, w.md, rho, u)
+    ora.step(100, coupled=False)
+    with gpu_sim([Replica(box, [], rep.seed)], w.md, F32, rho, u) as sim:
+        sim.step(100, coupled=False)
+        f = sim.populations()
+    err = max_rel(f, ora.f, _fluid(box))
+    log(f"  max rel err {err:.3e}")
+    assert err < 1e-5
+
+
+def _coupled_pair(w, storage, steps):
+    """Oracle and GPU advanced side by side; returns the smallest NGP decision margin
+    seen relative to the GPU-oracle bead position difference at that step."""
+    rep = w.replicas[0]
+    beads = G.replica_beads(rep, w.md)
+    ora = oracle_sim(rep, w.md, beads=beads)
+    sim = gpu_sim([rep], w.md, storage, beads=beads)
+    worst = np.inf
+    for _ in range(steps):
+        ora.step(1)
+        sim.step(1)
+        r, _ = sim.beads()
+        drift = float(np.max(np.abs(r - ora.r)))
+        worst = min(worst, min_tie_distance(ora.r) / max(drift, 1e-15))
+    return rep, ora, sim, worst
+
+
+# The bead dynamics at these parameters is chaotic: two oracle runs whose beads differ
+# by 1e-12 separate to ~1e-2 within 100 LB steps (see test_oracle_chaos.py), and the
+# FP64 GPU path, which differs from the oracle only in summation order, follows the
+# same growth.  Pointwise comparison of coupled runs is therefore made over 30 steps,
+# inside the horizon where the FP32 rounding differences have not been amplified;
+# longer runs are compared through their statistics.
+HORIZON = 30
+
+
+# bead positions: FP32 force rounding (~2e-7 after one step) grows chaotically to
+# ~3e-5 over the horizon, so they are held to 1e-4 in FP32
+@pytest.mark.parametrize("storage,pop_tol,pos_tol", [(F64, 1e-11, 1e-10), (F32, 1e-5, 1e-4)],
+                         ids=["f64", "f32"])
+def test_c2_coupled_pointwise(storage, pop_tol, pos_tol):
+    log(f"c2 coupled storage={storage}, {HORIZON} steps")
+    w = WC.c2_translocation(storage)
+    rep, ora, sim, worst = _coupled_pair(w, storage, HORIZON)
+    with sim:
+        f = sim.populations()
+        r, v = sim.beads()
+        tr = sim.transloc()
+        err_word, step = sim.status()
+        u_g, fb_g, node_g = sim.coupling()
+    log(f"  NGP margin / position drift (min over steps) {worst:.2e}; oracle flags {ora.flags}")
+    assert err_word == 0 and step == HORIZON
+    assert worst > 10.0, "an NGP decision fell within 10x the GPU-oracle position drift"
+    err = max_rel(f, ora.f, _fluid(rep.box))
+    log(f"  populations max rel err {err:.3e}; bead pos max abs err {np.max(np.abs(r - ora.r)):.3e}")
+    assert err < pop_tol
+    assert np.max(np.abs(r - ora.r)) < pos_tol
+    assert np.max(np.abs(v - ora.v)) < 100 * pos_tol
+    assert np.array_equal(node_g, ora.node)
+    assert np.max(np.abs(fb_g - ora.fbar)) < 100 * pos_tol
+    nt, com = O.transloc(rep.box, ora.r)
+    assert tr["n_t"] == nt
+    assert np.allclose(tr["com"], com, rtol=0, atol=pos_tol)
+
+
+def test_coupling_halves_equal_coupled_step():
+    w = WC.c2_translocation(F32)
+    rep = w.replicas[0]
+    beads = G.replica_beads(rep, w.md)
+    from paper_0710_1272_amd import lbmd as B
+    log("halves: interp, md, lb, spread == coupled")
+    with gpu_sim([rep], w.md, F32, beads=beads) as a, gpu_sim([rep], w.md, F32, beads=beads) as b:
+        a.step(3)
+        b.step(3)
+        a.step(1)
+        b.couple(B.LB_COUPLE_INTERP)
+        u_b, _, node_b = b.coupling()
+        b.md_step()
+        b.step(1, coupled=False)
+        b.couple(B.LB_COUPLE_SPREAD)
+        assert np.array_equal(a.populations(), b.populations())
+        ra, va = a.beads()
+        rb, vb = b.beads()
+        assert np.array_equal(ra, rb) and np.array_equal(va, vb)
+    # the interpolation half against the oracle on the same state
+    ora = oracle_sim(rep, w.md, beads=beads)
+    ora.step(3)
+    u_o, node_o = O.interp(rep.box, ora.f, ora.r)
+    assert np.array_equal(node_b, node_o)
+    assert np.max(np.abs(u_b - u_o)) < 1e-7
+
+
+def test_fp16_and_bf16_shear_wave_velocity():
+    box = Box(32, 32, 32, (PERIODIC,) * 3, (), 1.0)
+    rep = Replica(box, [], 1)
+    rho, u = G.shear_wave_fields(box, seed=rep.seed)
+    ora = oracle_sim(rep, MDParams(), rho, u)
+    ora.step(100, coupled=False)
+    _, u_ora = O.fields(box, ora.f)
+    umax = np.max(np.abs(u_ora))
+    errs = {}
+    for st in (F16, BF16):
+        with gpu_sim([rep], MDParams(), st, rho, u) as sim:
+            sim.step(100, coupled=False)
+            _, ug = sim.fields()
+        errs[st] = np.max(np.abs(ug - u_ora)) / umax
+    log(f"  16-bit velocity error / max|u|: fp16 {errs[F16]:.2e} bf16 {errs[BF16]:.2e}")
+    assert errs[F16] < 1e-3
+    assert errs[BF16] < 2e-2  # BF16 keeps 8 bits: reported, held to a looser bar
+
+
+def test_c2_coupled_fp16_velocity():
+    log(f"c2 coupled fp16, {HORIZON} steps")
+    w = WC.c2_translocation(F16)
+    rep, ora, sim, worst = _coupled_pair(w, F16, HORIZON)
+    with sim:
+        _, ug = sim.fields()
+    _, uo = O.fields(rep.box, ora.f)
+    fl = _fluid(rep.box)
+    umax = np.max(np.abs(uo[:, fl]))
+    err = np.max(np.abs(ug[:, fl] - uo[:, fl])) / umax
+    log(f"  fp16 coupled velocity err / max|u| = {err:.2e} (max|u| {umax:.2e}); margin {worst:.1f}")
+    assert worst > 10.0
+    assert err < 1e-3
+
+
+def test_momentum_exchange_conserves_total_fp64():
+    box = Box(16, 16, 16, (PERIODIC,) * 3, (), 0.9)
+    md = MDParams(M=20, gamma=0.2, f_drive=0.0)
+    rng = np.random.default_rng(5)
+    chain = G.grow_chain(box, md, 12, rng, cis_only=False)
+    rep = Replica(box, [12], 77)
+    rho, u = G.random_small_flow(box, 9, du=0.01)
+    v0 = 0.01 * rng.standard_normal(chain.shape)
+    with gpu_sim([rep], md, F64, rho, u, beads=chain, v=v0) as sim:
+        c0 = sim.conserved()
+        p0 = c0[1:] + md.mass * v0.sum(axis=0)
+        sim.step(20)
+        c1 = sim.conserved()
+        _, v = sim.beads()
+    p1 = c1[1:] + md.mass * v.sum(axis=0)
+    assert abs(c1[0] - c0[0]) < 1e-12 * c0[0]
+    assert np.allclose(p1, p0, rtol=0, atol=1e-12)
+
+
+def test_batched_replicas_match_single():
+    md = MDParams()
+    reps = [Replica(WC.pore_box(48, 48, 48), [30], 101), Replica(WC.pore_box(64, 64, 64), [55], 102),
+            Replica(WC.pore_box(80, 80, 80), [20], 103)]
+    beads = [G.replica_beads(r, md) for r in reps]
+    log("batched == single, 10 coupled steps, fp32")
+    with gpu_sim(reps, md, F32, beads=np.concatenate(beads)) as sim:
+        sim.step(10)
+        fb = [sim.populations(k) for k in range(3)]
+        rb = [sim.beads(k)[0] for k in range(3)]
+    for k, rep in enumerate(reps):
+        with gpu_sim([rep], md, F32, beads=beads[k]) as one:
+            one.step(10)
+            assert np.array_equal(one.populations(), fb[k])
+            assert np.array_equal(one.beads()[0], rb[k])
+    # and one replica against the oracle
+    ora = oracle_sim(reps[0], md, beads=beads[0])
+    ora.step(10)
+    assert max_rel(fb[0], ora.f, _fluid(reps[0].box)) < 1e-5
+
+
+def test_graph_and_direct_launches_bitwise_equal():
+    from paper_0710_1272_amd import lbmd as B
+    w = WC.c2_translocation(F32)
+    rep = w.replicas[0]
+    beads = G.replica_beads(rep, w.md)
+    out = []
+    for flags in (0, B.LB_CFG_NO_GRAPH, 0):
+        with gpu_sim([rep], w.md, F32, beads=beads, flags=flags) as sim:
+            sim.step(19)
+            out.append((sim.populations(), sim.beads()[0]))
+    for f, r in out[1:]:
+        assert np.array_equal(f, out[0][0]) and np.array_equal(r, out[0][1])
+
+
+def test_nan_density_sets_error_word():
+    from paper_0710_1272_amd import lbmd as B
+    box = Box(16, 8, 8, (PERIODIC,) * 3)
+    rho = np.ones(box.nodes)
+    rho[37] = np.nan
+    with gpu_sim([Replica(box, [], 0)], MDParams(), F32, rho=rho) as sim:
+        sim.step(1, coupled=False)
+        with pytest.raises(B.LBError) as e:
+            sim.conserved()
+        assert e.value.code == B.LB_EUNSTABLE
+        word, _ = sim.status()
+        assert word & B.LB_ERR_DENSITY

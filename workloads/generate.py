@@ -94,9 +94,10 @@ def grow_chain(box: Box, md: MDParams, n: int, rng: np.random.Generator,
 
 
 def pore_mouth(box: Box) -> np.ndarray:
-    """Centre of wall 0's pore on its cis face."""
+    """Just inside wall 0's pore, on its axis: 0.1 past the cis face plane x0 - 1/2,
+    so the bead's nearest node is a pore node without sitting on a rounding tie."""
     x0, _x1, y0, y1, z0, z1 = box.walls[0]
-    return np.array([x0 - 0.5, 0.5 * (y0 + y1), 0.5 * (z0 + z1)])
+    return np.array([x0 - 0.4, 0.5 * (y0 + y1), 0.5 * (z0 + z1)])
 
 
 def replica_beads(rep: Replica, md: MDParams, seed: Optional[int] = None) -> np.ndarray:
