@@ -58,7 +58,9 @@ __device__ __forceinline__ void gather19(const Replica& R, const typename Codec<
     // per-wall 3-bit masks: bit (d+1) set when x+d is a wall plane / y+d, z+d in the pore
     unsigned mx[LB_MAX_WALLS] = {0u, 0u}, mp[LB_MAX_WALLS] = {0u, 0u};
     if constexpr (KIND == G_WALL) {
-        for (int k = 0; k < R.n_walls; ++k) {
+#pragma unroll
+        for (int k = 0; k < LB_MAX_WALLS; ++k) {
+            if (k >= R.n_walls) break;
             const int* w = R.wall[k];
             unsigned bx = 0, by = 0, bz = 0;
 #pragma unroll
@@ -106,7 +108,9 @@ __device__ __forceinline__ void gather19(const Replica& R, const typename Codec<
             if constexpr (KIND == G_WALL && p != 0) {
                 // source offset is -c: bit (1 - c) of each mask
                 bool solid = false;
-                for (int k = 0; k < R.n_walls; ++k) {
+#pragma unroll
+                for (int k = 0; k < LB_MAX_WALLS; ++k) {
+                    if (k >= R.n_walls) break;
                     bool inx = (mx[k] >> (1 - cx)) & 1u;
                     bool inpore = (mp[k] >> (3 * (1 - cy) + (1 - cz))) & 1u;
                     solid = solid || (inx && !inpore);
@@ -181,7 +185,11 @@ __global__ __launch_bounds__(BLOCK) void k_stream_collide(const Replica* __restr
     if (active) {
         if (is_solid(R, x, y, z)) active = false;
         face = y == 0 || y == R.ny - 1 || z == 0 || z == R.nz - 1;
-        for (int k = 0; k < R.n_walls; ++k) zone = zone || (x >= R.wall[k][0] - 1 && x <= R.wall[k][1] + 1);
+#pragma unroll
+        for (int k = 0; k < LB_MAX_WALLS; ++k) {
+            if (k >= R.n_walls) break;
+            zone = zone || (x >= R.wall[k][0] - 1 && x <= R.wall[k][1] + 1);
+        }
     }
     face = face && active;
     zone = zone && active;

@@ -116,6 +116,8 @@ BeadLayout bead_layout(int ntot, int n_reps, size_t rs) {
     L.agg_f = off;    off += align256(3 * N * rs);
     L.rep_of = off;   off += align256(N * sizeof(int));
     L.diag = off;     off += align256(8 * (size_t)std::max(n_reps, 1) * sizeof(double));
+    L.nlist = off;    off += align256((size_t)kNeighbourMax * N * sizeof(unsigned short));
+    L.ncount = off;   off += align256(N * sizeof(int));
     L.total = off;
     return L;
 }
@@ -241,6 +243,8 @@ int setup_beads(Context& c, const lbmd_config* cfg) {
     p->agg_f = (Real*)(base + L.agg_f);
     p->rep_of = (int*)(base + L.rep_of);
     p->diag = (double*)(base + L.diag);
+    p->nlist = (unsigned short*)(base + L.nlist);
+    p->ncount = (int*)(base + L.ncount);
     p->ntot = c.ntot_beads;
     c.bead_ptrs = p;
 
@@ -509,6 +513,12 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
     md.eps_w = m.eps_w;
     md.sigma_w2 = m.sigma_w * m.sigma_w;
     md.rcw2 = std::pow(2.0, 1.0 / 3.0) * md.sigma_w2;
+    md.rcw = std::sqrt(md.rcw2);
+    // Verlet skin: the list holds pairs closer than rc + skin and is rebuilt as soon as
+    // any bead has moved skin/2 since the last build, so no interacting pair is missed
+    const double skin = 0.6;
+    md.rl2 = (std::sqrt(md.rc2) + skin) * (std::sqrt(md.rc2) + skin);
+    md.half_skin2 = 0.25 * skin * skin;
     md.f_drive = m.drive_sign * m.f_drive;
 
     // buffers

@@ -173,9 +173,13 @@ struct Replica {
 
 __host__ __device__ inline bool pore_open(const int* w) { return w[2] <= w[3] && w[4] <= w[5]; }
 
+// wall loops run over the compile-time maximum with a guard, so that the wall table
+// is indexed by constants (no private-array indexing)
 __host__ __device__ inline bool is_solid(const Replica& R, int x, int y, int z) {
     bool s = false;
-    for (int k = 0; k < R.n_walls; ++k) {
+#pragma unroll
+    for (int k = 0; k < LB_MAX_WALLS; ++k) {
+        if (k >= R.n_walls) break;
         const int* w = R.wall[k];
         bool inx = x >= w[0] && x <= w[1];
         bool pore = pore_open(w) && y >= w[2] && y <= w[3] && z >= w[4] && z <= w[5];
@@ -186,7 +190,9 @@ __host__ __device__ inline bool is_solid(const Replica& R, int x, int y, int z) 
 
 __host__ __device__ inline bool is_pore(const Replica& R, int x, int y, int z) {
     bool s = false;
-    for (int k = 0; k < R.n_walls; ++k) {
+#pragma unroll
+    for (int k = 0; k < LB_MAX_WALLS; ++k) {
+        if (k >= R.n_walls) break;
         const int* w = R.wall[k];
         s = s || (x >= w[0] && x <= w[1] && pore_open(w) && y >= w[2] && y <= w[3] && z >= w[4] &&
                   z <= w[5]);
@@ -311,6 +317,8 @@ __host__ __device__ inline R centred_uniform(uint32_t r) {
 // ---------------------------------------------------------------------------------
 // Device-side run state and bead buffers.
 // ---------------------------------------------------------------------------------
+constexpr int kNeighbourMax = 64;  // Verlet-list capacity per bead
+
 struct RunState {
     long long step;  // LB step counter (Philox counter word)
     unsigned err;    // error word, LB_ERR_* bits
@@ -328,7 +336,9 @@ struct BeadPtrs {
     int* agg_node;      // [Ntot] node of a bead that leads its node's sum, else -1
     Real* agg_f;        // [3][Ntot] summed Fbar of the beads sharing agg_node
     int* rep_of;        // [Ntot] replica of each bead
-    double* diag;       // [n_replicas][8]: N_T, t_done, com x,y,z, last step, -, -
+    double* diag;       // [n_replicas][8]: N_T, t_done, com x,y,z, last step, list builds, -
+    unsigned short* nlist;  // [kNeighbourMax][Ntot] Verlet neighbours (index within the replica)
+    int* ncount;        // [Ntot] number of neighbours; > kNeighbourMax means overflow
     int ntot;
 };
 

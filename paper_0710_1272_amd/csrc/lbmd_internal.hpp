@@ -18,7 +18,8 @@ struct MDDev {
     double mass, inv_mass, gamma, A;  // A = sqrt(24 m gamma kT / h)
     double k_bond, r0;
     double eps, sigma2, rc2;          // WCA bead-bead: rc^2 = 2^(1/3) sigma^2
-    double eps_w, sigma_w2, rcw2;     // WCA bead-surface
+    double eps_w, sigma_w2, rcw2, rcw; // WCA bead-surface
+    double rl2, half_skin2;           // Verlet list radius^2 (rc + skin)^2 and (skin/2)^2
     double f_drive;                   // signed along x
 };
 
@@ -86,7 +87,7 @@ WorkLayout work_layout(int n_reps, int max_V, long long max_stage_nodes);
 
 // bead-buffer layout
 struct BeadLayout {
-    size_t r, v, u, fbar, node, bond_next, agg_node, agg_f, rep_of, diag, total;
+    size_t r, v, u, fbar, node, bond_next, agg_node, agg_f, rep_of, diag, nlist, ncount, total;
 };
 BeadLayout bead_layout(int ntot, int n_reps, size_t real_size);
 

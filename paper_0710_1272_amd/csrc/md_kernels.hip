@@ -51,6 +51,7 @@ struct MDKArgs {
     RunState* st;
     int mode;
     int nmax;
+    int list_in_lds;
 };
 
 // nearest node: floor(r + 1/2); periodic axes wrap, free-slip axes clamp (NaN -> 0)
@@ -80,15 +81,19 @@ __device__ inline double wall_distance(const Replica& R, const double* rin, doub
     double r[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) r[a] = R.fs[a] ? rin[a] : rin[a] - n[a] * floor((rin[a] + 0.5) / n[a]);
-    double best = HUGE_VAL;
+    double best2 = HUGE_VAL;
     dv[0] = dv[1] = dv[2] = 0.0;
-    for (int k = 0; k < R.n_walls; ++k) {
+#pragma unroll
+    for (int k = 0; k < LB_MAX_WALLS; ++k) {
+        if (k >= R.n_walls) break;
         const int* w = R.wall[k];
         const double X0 = w[0] - 0.5, X1 = w[1] + 0.5;
         const bool open = pore_open(w);
         const double Y0 = w[2] - 0.5, Y1 = w[3] + 0.5, Z0 = w[4] - 0.5, Z1 = w[5] + 0.5;
         const int nb = open ? 4 : 1;
-        for (int m = 0; m < nb; ++m) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            if (m >= nb) break;
             double lo[3] = {X0, -HUGE_VAL, -HUGE_VAL}, hi[3] = {X1, HUGE_VAL, HUGE_VAL};
             if (open) {
                 if (m == 0) { hi[1] = Y0; }
@@ -103,25 +108,132 @@ __device__ inline double wall_distance(const Replica& R, const double* rin, doub
                 d[a] = r[a] - c;
                 d2 += d[a] * d[a];
             }
-            const double dist = sqrt(d2);
-            if (dist < best) {
-                best = dist;
+            if (d2 < best2) {
+                best2 = d2;
                 dv[0] = d[0];
                 dv[1] = d[1];
                 dv[2] = d[2];
             }
         }
     }
-    return best;
+    return sqrt(best2);
+}
+
+// The part of a replica's description the substep loop reads, copied into registers
+// at kernel entry (before any store, so the copy is made with scalar loads).
+struct Geom {
+    int n[3];
+    int fs[3];
+    int n_walls;
+    int wall[LB_MAX_WALLS][6];
+};
+
+__device__ __forceinline__ Geom load_geom(const Replica& R) {
+    // every field is the same for the whole workgroup: keep it in scalar registers
+    auto u = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
+    Geom g;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) g.fs[a] = u(R.fs[a]);
+    g.n[0] = u(R.nx);
+    g.n[1] = u(R.ny);
+    g.n[2] = u(R.nz);
+    g.n_walls = u(R.n_walls);
+#pragma unroll
+    for (int k = 0; k < LB_MAX_WALLS; ++k)
+#pragma unroll
+        for (int m = 0; m < 6; ++m) g.wall[k][m] = u(R.wall[k][m]);
+    return g;
+}
+
+__device__ __forceinline__ bool geom_is_pore(const Geom& G, const int* c) {
+    bool s = false;
+#pragma unroll
+    for (int k = 0; k < LB_MAX_WALLS; ++k) {
+        if (k >= G.n_walls) break;
+        const int* w = G.wall[k];
+        s = s || (c[0] >= w[0] && c[0] <= w[1] && pore_open(w) && c[1] >= w[2] && c[1] <= w[3] &&
+                  c[2] >= w[4] && c[2] <= w[5]);
+    }
+    return s;
+}
+
+// nearest node floor(r + 1/2): free-slip axes clamp (NaN -> 0), periodic axes wrap
+template <bool PERIODIC>
+__device__ __forceinline__ void geom_ngp(const Geom& G, const double* r, int* c) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double t = floor(r[a] + 0.5);
+        if (!(t >= -1e9 && t <= 1e9)) t = 0.0;  // non-finite or absurd
+        int k = (int)t;
+        if (PERIODIC && !G.fs[a]) {
+            k %= G.n[a];
+            if (k < 0) k += G.n[a];
+        } else {
+            k = k < 0 ? 0 : (k > G.n[a] - 1 ? G.n[a] - 1 : k);
+        }
+        c[a] = k;
+    }
+}
+
+// distance to the nearest solid surface and the vector from it to r (see wall_distance)
+template <bool PERIODIC>
+__device__ inline double geom_wall_distance(const Geom& G, const double* rin, double* dv) {
+    double r[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        r[a] = (PERIODIC && !G.fs[a]) ? rin[a] - G.n[a] * floor((rin[a] + 0.5) / G.n[a]) : rin[a];
+    double best2 = HUGE_VAL;
+    dv[0] = dv[1] = dv[2] = 0.0;
+#pragma unroll
+    for (int k = 0; k < LB_MAX_WALLS; ++k) {
+        if (k >= G.n_walls) break;
+        const int* w = G.wall[k];
+        const double X0 = w[0] - 0.5, X1 = w[1] + 0.5;
+        const bool open = pore_open(w);
+        const double Y0 = w[2] - 0.5, Y1 = w[3] + 0.5, Z0 = w[4] - 0.5, Z1 = w[5] + 0.5;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            if (m >= (open ? 4 : 1)) break;
+            double lo[3] = {X0, -HUGE_VAL, -HUGE_VAL}, hi[3] = {X1, HUGE_VAL, HUGE_VAL};
+            if (open) {
+                if (m == 0) { hi[1] = Y0; }
+                else if (m == 1) { lo[1] = Y1; }
+                else if (m == 2) { lo[1] = Y0; hi[1] = Y1; hi[2] = Z0; }
+                else { lo[1] = Y0; hi[1] = Y1; lo[2] = Z1; }
+            }
+            double d[3], d2 = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double c = fmin(fmax(r[a], lo[a]), hi[a]);
+                d[a] = r[a] - c;
+                d2 += d[a] * d[a];
+            }
+            if (d2 < best2) {
+                best2 = d2;
+                dv[0] = d[0];
+                dv[1] = d[1];
+                dv[2] = d[2];
+            }
+        }
+    }
+    return sqrt(best2);
+}
+
+// 1/x: the hardware reciprocal in FP32 (about 1 ulp), an exact division in FP64
+template <class Real>
+__device__ __forceinline__ Real fast_rcp(Real x) {
+    if constexpr (sizeof(Real) == 4) return __builtin_amdgcn_rcpf(x);
+    else return Real(1) / x;
 }
 
 // -(1/r) dV/dr of WCA at squared distance r2 (0 beyond the cutoff)
 template <class Real>
 __device__ __forceinline__ Real wca_coef(Real r2, Real eps, Real sig2, Real rc2) {
     if (!(r2 < rc2)) return Real(0);
-    const Real s2 = sig2 / r2;
+    const Real ir2 = fast_rcp<Real>(r2);
+    const Real s2 = sig2 * ir2;
     const Real s6 = s2 * s2 * s2;
-    return Real(24) * eps * (Real(2) * s6 * s6 - s6) / r2;
+    return Real(24) * eps * (Real(2) * s6 * s6 - s6) * ir2;
 }
 
 template <class Real>
@@ -190,31 +302,105 @@ __device__ __forceinline__ T group_sum(T v) {
     return v;
 }
 
-// Each bead is owned by a group of G lanes that split its partner loop; every lane
-// of the group keeps the bead's state, so the per-bead terms are computed
-// redundantly without divergence.  BPT beads per group when there are more beads
-// than groups (then G = 1).
-template <class Real, int BLOCK, int G, int BPT, bool PERIODIC>
-__global__ __launch_bounds__(BLOCK) void k_md(MDKArgs<Real> a, int storage) {
+// Pairwise separation r_i - r_j as FP32/FP64 components (minimum image on periodic
+// axes) and its square.
+template <class Real, bool PERIODIC>
+__device__ __forceinline__ Real separation(const double* ri, const double* PX, const double* PY,
+                                           const double* PZ, int j, const int* per, const double* nd,
+                                           Real* d) {
+    double dd[3] = {ri[0] - PX[j], ri[1] - PY[j], ri[2] - PZ[j]};
+    if constexpr (PERIODIC) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if (per[c]) dd[c] -= nd[c] * floor(dd[c] / nd[c] + 0.5);
+    }
+    d[0] = (Real)dd[0];
+    d[1] = (Real)dd[1];
+    d[2] = (Real)dd[2];
+    return d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+}
+
+// Verlet list of bead i (group of G lanes): every non-bonded bead closer than the list
+// radius, in lane-then-index order.  Returns the count (may exceed the capacity).
+template <class Real, int G, bool PERIODIC>
+__device__ __forceinline__ int build_list(int i, int n, bool bn, bool bp, const double* ri, const double* PX,
+                                          const double* PY, const double* PZ, const int* per,
+                                          const double* nd, Real rl2, int gl, unsigned short* list,
+                                          int stride) {
+    if constexpr (G == 1) {
+        // one lane per bead: append directly, keep counting past the capacity
+        int total = 0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i || (j == i + 1 && bn) || (j == i - 1 && bp)) continue;
+            Real d[3];
+            if (separation<Real, PERIODIC>(ri, PX, PY, PZ, j, per, nd, d) < rl2) {
+                if (total < kNeighbourMax) list[(size_t)total * stride] = (unsigned short)j;
+                ++total;
+            }
+        }
+        return total;
+    } else {
+        int mine = 0;
+        for (int j = gl; j < n; j += G) {
+            if (j == i || (j == i + 1 && bn) || (j == i - 1 && bp)) continue;
+            Real d[3];
+            if (separation<Real, PERIODIC>(ri, PX, PY, PZ, j, per, nd, d) < rl2) ++mine;
+        }
+        // exclusive prefix over the group's lanes
+        int incl = mine;
+#pragma unroll
+        for (int off = 1; off < G; off <<= 1) {
+            const int t = __shfl_up(incl, off, G);
+            if (gl >= off) incl += t;
+        }
+        int pos = incl - mine;
+        const int total = __shfl(incl, G - 1, G);
+        if (total <= kNeighbourMax) {
+            for (int j = gl; j < n; j += G) {
+                if (j == i || (j == i + 1 && bn) || (j == i - 1 && bp)) continue;
+                Real d[3];
+                if (separation<Real, PERIODIC>(ri, PX, PY, PZ, j, per, nd, d) < rl2)
+                    list[(size_t)(pos++) * stride] = (unsigned short)j;
+            }
+        }
+        return total;
+    }
+}
+
+// Each bead is owned by a group of G lanes that split its neighbour loop; every lane
+// of the group keeps the bead's state, so the per-bead terms are computed redundantly
+// without divergence.  BPT beads per group when there are more beads than groups
+// (then G = 1).  WCA pairs come from a Verlet list (radius rc + skin) rebuilt at the
+// start of every LB step and whenever a bead has moved skin/2 since the last build,
+// so the set of interacting pairs is exactly that of the all-pairs definition.
+// Positions are double-buffered in LDS: one barrier per substep.
+template <class Real, int G, int BPT, bool PERIODIC, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
     extern __shared__ double lds[];
     __shared__ double red[16 * 4];
-    constexpr int NG = BLOCK / G;  // groups per block
+    const int NG = blockDim.x / G;  // groups per block
     const Replica& R = a.reps[blockIdx.x];
+    const Geom GM = load_geom(R);
+    const uint32_t seed_lo = R.seed_lo, seed_hi = R.seed_hi;
+    const double xmid = R.xmid;
     const int n = R.n_beads;
     if (n == 0) return;
-    const int b0 = R.bead0, NT = a.b.ntot, tid = threadIdx.x;
+    const int b0 = R.bead0, NT = a.b.ntot, tid = threadIdx.x, nmax = a.nmax;
     const int grp = tid / G, gl = tid % G;
-    double* PX = lds;
-    double* PY = PX + a.nmax;
-    double* PZ = PY + a.nmax;
-    int* NODE = (int*)(PZ + a.nmax);
-    unsigned char* BN = (unsigned char*)(NODE + a.nmax);
-    const MDDev& md = a.md;
+    double* P = lds;                                    // [2][3][nmax] positions
+    int* NODE = (int*)(P + 6 * nmax);                   // [nmax]
+    unsigned char* BN = (unsigned char*)(NODE + nmax);  // [nmax]
+    // Verlet lists: [kNeighbourMax][nmax] in LDS when they fit, else global memory
+    unsigned short* lists = a.list_in_lds ? (unsigned short*)(BN + nmax) : a.b.nlist + b0;
+    const int lstride = a.list_in_lds ? nmax : NT;
+    const MDDev md = a.md;
+    const int M = md.M;
     const long long step = a.st->step;
-    const int nn[3] = {R.nx, R.ny, R.nz};
-    const double nd[3] = {(double)R.nx, (double)R.ny, (double)R.nz};
-    const int per[3] = {R.fs[0] ? 0 : 1, R.fs[1] ? 0 : 1, R.fs[2] ? 0 : 1};
+    const int* nn = GM.n;
+    const double nd[3] = {(double)GM.n[0], (double)GM.n[1], (double)GM.n[2]};
+    const int per[3] = {GM.fs[0] ? 0 : 1, GM.fs[1] ? 0 : 1, GM.fs[2] ? 0 : 1};
     unsigned flags = 0;
+    int cur = 0;
 
     double r[BPT][3];
     Real v[BPT][3], u[BPT][3], fb[BPT][3];
@@ -235,9 +421,8 @@ __global__ __launch_bounds__(BLOCK) void k_md(MDKArgs<Real> a, int storage) {
                 v[k][c] = a.b.v[c * NT + g];
             }
             if (gl == 0) {
-                PX[i] = r[k][0];
-                PY[i] = r[k][1];
-                PZ[i] = r[k][2];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) P[c * nmax + i] = r[k][c];
                 BN[i] = a.b.bond_next[g];
             }
         }
@@ -276,15 +461,66 @@ __global__ __launch_bounds__(BLOCK) void k_md(MDKArgs<Real> a, int storage) {
         }
     }
     if (!(a.mode & MD_SUBSTEPS)) return;
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+        const int i = grp + k * NG;
+        if (own[k] && gl == 0) NODE[i] = node[k];
+    }
 
     const Real h = (Real)md.h, hm = (Real)(md.h * md.inv_mass), invM = (Real)md.inv_M;
     const Real mg = (Real)(md.mass * md.gamma), A = (Real)md.A;
     const Real kb = (Real)md.k_bond, r0 = (Real)md.r0;
     const Real eps24 = (Real)(24.0 * md.eps), sig2 = (Real)md.sigma2, rc2 = (Real)md.rc2;
     const Real epsw = (Real)md.eps_w, sigw2 = (Real)md.sigma_w2, rcw2 = (Real)md.rcw2;
+    const double rcw = md.rcw;
+    const Real rl2 = (Real)md.rl2, hs2 = (Real)md.half_skin2;
     const Real fdrive = (Real)md.f_drive;
 
-    for (int sub = 0; sub < md.M; ++sub) {
+    // neighbour lists (reference positions kept in registers)
+    double rref[BPT][3];
+    int cnt[BPT];
+    int builds = 1;
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+        const int i = grp + k * NG;
+        cnt[k] = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rref[k][c] = r[k][c];
+        if (!own[k]) continue;
+        cnt[k] = build_list<Real, G, PERIODIC>(i, n, BN[i] != 0, i > 0 && BN[i - 1] != 0, r[k], P, P + nmax,
+                                               P + 2 * nmax, per, nd, rl2, gl, lists + i, lstride);
+    }
+    __syncthreads();
+    // Beads on one node at the start of the step are closer than sqrt(3) < rc, so they
+    // are bonded neighbours or in this list: flag whether a bead shares its node and
+    // whether a lower-index bead does (then it is not the node's leader).
+    bool shared[BPT], before[BPT];
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+        const int i = grp + k * NG;
+        int sh = 0, bf = 0;
+        if (own[k] && node[k] >= 0) {
+            const bool ovf = cnt[k] > kNeighbourMax;
+            const int lim = ovf ? n : cnt[k] + 2;
+            for (int q = gl; q < lim; q += G) {
+                int j;
+                if (ovf) j = q;
+                else if (q < cnt[k]) j = lists[i + q * lstride];
+                else j = (q == cnt[k]) ? i - 1 : i + 1;
+                if (j < 0 || j >= n || j == i || NODE[j] != node[k]) continue;
+                sh = 1;
+                if (j < i) bf = 1;
+            }
+        }
+        shared[k] = group_sum<G>(sh) != 0;
+        before[k] = group_sum<G>(bf) != 0;
+    }
+
+    for (int sub = 0; sub < M; ++sub) {
+        const double* PX = P + cur * 3 * nmax;
+        const double* PY = PX + nmax;
+        const double* PZ = PY + nmax;
+        double* QX = P + (cur ^ 1) * 3 * nmax;
         Real F[BPT][3];
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
@@ -293,26 +529,29 @@ __global__ __launch_bounds__(BLOCK) void k_md(MDKArgs<Real> a, int storage) {
             if (!own[k]) continue;
             const bool bn = BN[i] != 0;
             const bool bp = i > 0 && BN[i - 1] != 0;
-            // WCA against every non-bonded bead: this lane takes j = gl, gl + G, ...
+            // WCA against the Verlet neighbours (all pairs if the list overflowed)
             Real fx = 0, fy = 0, fz = 0;
-            for (int j = gl; j < n; j += G) {
-                if (j == i || (j == i + 1 && bn) || (j == i - 1 && bp)) continue;
-                double ddx = r[k][0] - PX[j], ddy = r[k][1] - PY[j], ddz = r[k][2] - PZ[j];
-                if constexpr (PERIODIC) {
-                    if (per[0]) ddx -= nd[0] * floor(ddx / nd[0] + 0.5);
-                    if (per[1]) ddy -= nd[1] * floor(ddy / nd[1] + 0.5);
-                    if (per[2]) ddz -= nd[2] * floor(ddz / nd[2] + 0.5);
+            const bool overflow = cnt[k] > kNeighbourMax;
+            const int lim = overflow ? n : cnt[k];
+            const unsigned short* li = lists + i;
+            for (int q = gl; q < lim; q += G) {
+                int j;
+                if (overflow) {
+                    j = q;
+                    if (j == i || (j == i + 1 && bn) || (j == i - 1 && bp)) continue;
+                } else {
+                    j = li[q * lstride];
                 }
-                const Real dx = (Real)ddx, dy = (Real)ddy, dz = (Real)ddz;
-                const Real r2 = dx * dx + dy * dy + dz * dz;
+                Real d[3];
+                const Real r2 = separation<Real, PERIODIC>(r[k], PX, PY, PZ, j, per, nd, d);
                 if (r2 < rc2) {
-                    const Real ir2 = Real(1) / r2;
+                    const Real ir2 = fast_rcp<Real>(r2);
                     const Real s2 = sig2 * ir2;
                     const Real s6 = s2 * s2 * s2;
                     const Real c = eps24 * (Real(2) * s6 * s6 - s6) * ir2;
-                    fx += c * dx;
-                    fy += c * dy;
-                    fz += c * dz;
+                    fx += c * d[0];
+                    fy += c * d[1];
+                    fz += c * d[2];
                 }
             }
             F[k][0] = group_sum<G>(fx);
@@ -324,24 +563,25 @@ __global__ __launch_bounds__(BLOCK) void k_md(MDKArgs<Real> a, int storage) {
                 const bool on = side == 0 ? bp : bn;
                 if (!on) continue;
                 const int j = side == 0 ? i - 1 : i + 1;
-                double dd[3] = {PX[j] - r[k][0], PY[j] - r[k][1], PZ[j] - r[k][2]};
-                if constexpr (PERIODIC) {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        if (per[c]) dd[c] -= nd[c] * floor(dd[c] / nd[c] + 0.5);
-                }
-                const Real d[3] = {(Real)dd[0], (Real)dd[1], (Real)dd[2]};
-                const Real len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                Real d[3];
+                const Real len = sqrt(separation<Real, PERIODIC>(r[k], PX, PY, PZ, j, per, nd, d));
                 if (len > Real(2) * r0) flags |= LB_ERR_BOND_STRETCH;
-                const Real coef = kb * (len - r0) / len;
+                // d points from j to i: the bond pulls i towards j when stretched
+                const Real coef = -kb * (len - r0) * fast_rcp<Real>(len);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) F[k][c] += coef * d[c];
             }
-            // nearest solid surface
+            // nearest solid surface (only near a wall)
             if (!(isfinite(r[k][0]) && isfinite(r[k][1]) && isfinite(r[k][2]))) flags |= LB_ERR_NONFINITE;
-            if (R.n_walls > 0) {
+            bool near_wall = false;
+#pragma unroll
+            for (int w = 0; w < LB_MAX_WALLS; ++w) {
+                if (w >= GM.n_walls) break;
+                near_wall = near_wall || (r[k][0] > GM.wall[w][0] - 0.5 - rcw && r[k][0] < GM.wall[w][1] + 0.5 + rcw);
+            }
+            if (near_wall) {
                 double dv[3];
-                const double dist = wall_distance(R, r[k], dv);
+                const double dist = geom_wall_distance<PERIODIC>(GM, r[k], dv);
                 if (dist == 0.0) {
                     flags |= LB_ERR_BEAD_IN_SOLID;
                 } else {
@@ -353,7 +593,7 @@ __global__ __launch_bounds__(BLOCK) void k_md(MDKArgs<Real> a, int storage) {
             // free-slip faces at -1/2 and n - 1/2
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                if (!R.fs[c]) continue;
+                if (!GM.fs[c]) continue;
                 const Real dlo = (Real)(r[k][c] + 0.5), dhi = (Real)((nn[c] - 0.5) - r[k][c]);
                 if (!(dlo > Real(0)) || !(dhi > Real(0))) {
                     flags |= LB_ERR_BEAD_OUTSIDE;
@@ -364,11 +604,10 @@ __global__ __launch_bounds__(BLOCK) void k_md(MDKArgs<Real> a, int storage) {
             }
             // pulling force on beads whose nearest node is a pore node
             int g[3];
-            ngp3(R, r[k], g);
-            if (is_pore(R, g[0], g[1], g[2])) F[k][0] += fdrive;
+            geom_ngp<PERIODIC>(GM, r[k], g);
+            if (geom_is_pore(GM, g)) F[k][0] += fdrive;
             // drag against the frozen fluid velocity and the random force
-            const U4 rnd = philox4x32_10(U4{(uint32_t)i, (uint32_t)step, (uint32_t)sub, 1u}, R.seed_lo,
-                                         R.seed_hi);
+            const U4 rnd = philox4x32_10(U4{(uint32_t)i, (uint32_t)step, (uint32_t)sub, 1u}, seed_lo, seed_hi);
             const uint32_t rr[3] = {rnd.x, rnd.y, rnd.z};
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -378,23 +617,43 @@ __global__ __launch_bounds__(BLOCK) void k_md(MDKArgs<Real> a, int storage) {
                 fb[k][c] += (drag + noise) * invM;
             }
         }
-        __syncthreads();  // every read of the old positions is done
+        // kick-drift into the other position buffer; the single barrier below both
+        // publishes the new positions and votes on a list rebuild
+        int moved = 0;
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
             const int i = grp + k * NG;
             if (!own[k]) continue;
+            Real disp2 = 0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 v[k][c] += hm * F[k][c];
                 r[k][c] += (double)(h * v[k][c]);
+                const Real dd = (Real)(r[k][c] - rref[k][c]);
+                disp2 += dd * dd;
             }
+            moved |= !(disp2 <= hs2);  // also catches a non-finite position
             if (gl == 0) {
-                PX[i] = r[k][0];
-                PY[i] = r[k][1];
-                PZ[i] = r[k][2];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) QX[c * nmax + i] = r[k][c];
             }
         }
-        __syncthreads();
+        cur ^= 1;
+        if (__syncthreads_or(moved) && sub + 1 < M) {
+            ++builds;
+            const double* NX = P + cur * 3 * nmax;
+#pragma unroll
+            for (int k = 0; k < BPT; ++k) {
+                const int i = grp + k * NG;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) rref[k][c] = r[k][c];
+                if (!own[k]) continue;
+                cnt[k] = build_list<Real, G, PERIODIC>(i, n, BN[i] != 0, i > 0 && BN[i - 1] != 0, r[k], NX,
+                                                       NX + nmax, NX + 2 * nmax, per, nd, rl2, gl, lists + i,
+                                                       lstride);
+            }
+            __syncthreads();
+        }
     }
 
     // write back, translocation count, centre of mass
@@ -410,22 +669,22 @@ __global__ __launch_bounds__(BLOCK) void k_md(MDKArgs<Real> a, int storage) {
             a.b.v[c * NT + gi] = v[k][c];
             a.b.fbar[c * NT + gi] = fb[k][c];
         }
-        acc[0] += r[k][0] > R.xmid ? 1.0 : 0.0;
+        acc[0] += r[k][0] > xmid ? 1.0 : 0.0;
         acc[1] += r[k][0];
         acc[2] += r[k][1];
         acc[3] += r[k][2];
     }
     block_sums<Real>(acc, 4, red);
 
-    // one leader per occupied node (its lowest-index bead) sums the Fbar of the beads on it
+    // one leader per occupied node (its lowest-index bead) sums the Fbar of the beads on
+    // it in index order; a bead alone on its node is its own sum
+    double* FX = P;  // positions are no longer needed
 #pragma unroll
     for (int k = 0; k < BPT; ++k) {
         const int i = grp + k * NG;
         if (!own[k] || gl != 0) continue;
-        NODE[i] = node[k];
-        PX[i] = (double)fb[k][0];
-        PY[i] = (double)fb[k][1];
-        PZ[i] = (double)fb[k][2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) FX[c * nmax + i] = (double)fb[k][c];
     }
     __syncthreads();
 #pragma unroll
@@ -433,29 +692,23 @@ __global__ __launch_bounds__(BLOCK) void k_md(MDKArgs<Real> a, int storage) {
         const int i = grp + k * NG;
         if (!own[k]) continue;
         const int me = node[k];
-        int before = 0;
-        Real s[3] = {0, 0, 0};
-        if (me >= 0) {
-            for (int j = gl; j < n; j += G) {
-                if (NODE[j] != me) continue;
-                if (j < i) {
-                    before = 1;
-                } else {
-                    s[0] += (Real)PX[j];
-                    s[1] += (Real)PY[j];
-                    s[2] += (Real)PZ[j];
+        const bool lead = me >= 0 && !before[k];
+        Real s[3] = {fb[k][0], fb[k][1], fb[k][2]};
+        if (lead && shared[k]) {
+            Real t[3] = {0, 0, 0};
+            for (int j = i + 1 + gl; j < n; j += G)
+                if (NODE[j] == me) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) t[c] += (Real)FX[c * nmax + j];
                 }
-            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s[c] += group_sum<G>(t[c]);
         }
-        before = group_sum<G>(before);
-        s[0] = group_sum<G>(s[0]);
-        s[1] = group_sum<G>(s[1]);
-        s[2] = group_sum<G>(s[2]);
         if (gl == 0) {
             const int gi = b0 + i;
-            a.b.agg_node[gi] = (me >= 0 && before == 0) ? me : -1;
+            a.b.agg_node[gi] = lead ? me : -1;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) a.b.agg_f[c * NT + gi] = s[c];
+            for (int c = 0; c < 3; ++c) a.b.agg_f[c * NT + gi] = lead ? s[c] : Real(0);
         }
     }
     if (tid == 0) {
@@ -466,6 +719,7 @@ __global__ __launch_bounds__(BLOCK) void k_md(MDKArgs<Real> a, int storage) {
         dg[3] = acc[2] / n;
         dg[4] = acc[3] / n;
         dg[5] = (double)(step + 1);
+        dg[6] += (double)builds;
     }
     if (flags) atomicOr(&a.st->err, flags);
 }
@@ -510,13 +764,23 @@ __global__ void k_bump(RunState* st) { st->step += 1; }
 // ---------------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------------
-size_t md_lds_bytes(const Context& c) {
-    const size_t nmax = (size_t)((c.max_beads + 63) / 64 * 64);
-    return nmax * (3 * sizeof(double) + sizeof(int) + 1);
+static int md_nmax(const Context& c) { return (c.max_beads + 63) / 64 * 64; }
+
+// Verlet lists go to LDS when positions (two buffers), node/bond arrays and lists fit
+static bool md_lists_in_lds(const Context& c) {
+    const size_t nmax = (size_t)md_nmax(c);
+    return nmax * (6 * sizeof(double) + sizeof(int) + 1 + kNeighbourMax * sizeof(unsigned short)) <= 150 * 1024;
 }
 
-template <class Real, int G, int BPT, bool PER>
-static hipError_t launch_md_t(const Context& c, const void* cur, int mode, hipStream_t s) {
+size_t md_lds_bytes(const Context& c) {
+    const size_t nmax = (size_t)md_nmax(c);
+    size_t b = nmax * (6 * sizeof(double) + sizeof(int) + 1);
+    if (md_lists_in_lds(c)) b += nmax * kNeighbourMax * sizeof(unsigned short);
+    return b;
+}
+
+template <class Real, int G, int BPT, bool PER, int MAXT>
+static hipError_t launch_md_t(const Context& c, const void* cur, int mode, int block, hipStream_t s) {
     MDKArgs<Real> a;
     a.reps = c.d_reps;
     a.md = c.md;
@@ -524,33 +788,38 @@ static hipError_t launch_md_t(const Context& c, const void* cur, int mode, hipSt
     a.cur = cur;
     a.st = c.d_state;
     a.mode = mode;
-    a.nmax = (c.max_beads + 63) / 64 * 64;
+    a.nmax = md_nmax(c);
+    a.list_in_lds = md_lists_in_lds(c) ? 1 : 0;
     const size_t lds = md_lds_bytes(c);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_md<Real, 1024, G, BPT, PER>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_md<Real, G, BPT, PER, MAXT>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_md<Real, 1024, G, BPT, PER>), dim3((unsigned)c.reps.size()), dim3(1024), lds, s, a,
+    hipLaunchKernelGGL((k_md<Real, G, BPT, PER, MAXT>), dim3((unsigned)c.reps.size()), dim3(block), lds, s, a,
                        c.storage);
     return hipGetLastError();
 }
 
 template <class Real, bool PER>
 static hipError_t launch_md_g(const Context& c, const void* cur, int mode, hipStream_t s) {
-    // lanes per bead: as many as fit 1024 threads (at most 32); beyond 1024 beads,
-    // one lane per bead and up to 4 beads per lane
+    // lanes per bead: up to ~512 threads, so that each SIMD has two waves to interleave
+    // (measured faster than one wave per SIMD for 100 beads, although the per-bead work
+    // is repeated by every lane of a group); beyond 256 beads one lane per bead, beyond
+    // 512 the 1024-thread bound, beyond 1024 up to 4 beads per lane
     const int m = std::max(c.max_beads, 1);
-    if (m <= 32) return launch_md_t<Real, 32, 1, PER>(c, cur, mode, s);
-    if (m <= 64) return launch_md_t<Real, 16, 1, PER>(c, cur, mode, s);
-    if (m <= 128) return launch_md_t<Real, 8, 1, PER>(c, cur, mode, s);
-    if (m <= 256) return launch_md_t<Real, 4, 1, PER>(c, cur, mode, s);
-    if (m <= 512) return launch_md_t<Real, 2, 1, PER>(c, cur, mode, s);
-    if (m <= 1024) return launch_md_t<Real, 1, 1, PER>(c, cur, mode, s);
-    if (m <= 2048) return launch_md_t<Real, 1, 2, PER>(c, cur, mode, s);
-    if (m <= 4096) return launch_md_t<Real, 1, 4, PER>(c, cur, mode, s);
+    auto blk = [](int t) { return std::min(1024, (t + 63) / 64 * 64); };
+    if (m <= 32) return launch_md_t<Real, 16, 1, PER, 512>(c, cur, mode, blk(16 * m), s);
+    if (m <= 64) return launch_md_t<Real, 8, 1, PER, 512>(c, cur, mode, blk(8 * m), s);
+    if (m <= 128) return launch_md_t<Real, 4, 1, PER, 512>(c, cur, mode, blk(4 * m), s);
+    if (m <= 256) return launch_md_t<Real, 2, 1, PER, 512>(c, cur, mode, blk(2 * m), s);
+    if (m <= 512) return launch_md_t<Real, 1, 1, PER, 512>(c, cur, mode, blk(m), s);
+    if (m <= 1024) return launch_md_t<Real, 1, 1, PER, 1024>(c, cur, mode, blk(m), s);
+    if (m <= 2048) return launch_md_t<Real, 1, 2, PER, 1024>(c, cur, mode, 1024, s);
+    if (m <= 3072) return launch_md_t<Real, 1, 3, PER, 1024>(c, cur, mode, 1024, s);
+    if (m <= 4096) return launch_md_t<Real, 1, 4, PER, 1024>(c, cur, mode, 1024, s);
     return hipErrorInvalidValue;
 }
 

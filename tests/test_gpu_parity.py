@@ -280,3 +280,76 @@ def test_nan_density_sets_error_word():
         assert e.value.code == B.LB_EUNSTABLE
         word, _ = sim.status()
         assert word & B.LB_ERR_DENSITY
+
+
+def _dense_chain(box, n, seed, sigma_gen=1.75):
+    """A chain packed closer than the WCA range (exclusion 2^(1/6) * 1.75 < 2^(1/6) * 1.8),
+    so that bead-bead repulsion is active from the first substep."""
+    import dataclasses
+    md_gen = dataclasses.replace(MDParams(), sigma=sigma_gen)
+    return G.grow_chain(box, md_gen, n, np.random.default_rng(seed), cis_only=False)
+
+
+@pytest.mark.parametrize("storage,tol", [(F64, 1e-11), (F32, 2e-4)], ids=["f64", "f32"])
+@pytest.mark.parametrize("periodic", [False, True], ids=["pore", "periodic"])
+def test_md_step_dense_contacts(storage, tol, periodic):
+    """One INTERP + md_step (20 substeps) with WCA contacts, wall, pore and faces (or
+    periodic images) against the oracle's interpolation and substeps."""
+    if periodic:
+        box = Box(20, 16, 16, (PERIODIC,) * 3, (), 1.0)
+        chains = [40, 8]
+    else:
+        box = Box(40, 24, 24, (FREESLIP,) * 3, ((18, 20, 10, 12, 10, 12),), 1.0)
+        chains = [60, 8]
+    md = MDParams()
+    a = _dense_chain(box, chains[0], 1)
+    b = G.grow_chain(box, md, chains[1], np.random.default_rng(2), existing=a, cis_only=False)
+    if periodic:
+        a = a + np.array([12.0, 0.0, 0.0])  # let the chain cross the periodic x boundary
+    beads = np.concatenate([a, b])
+    rep = Replica(box, chains, 31)
+    rho, u = G.random_small_flow(box, 5, du=0.01)
+    from paper_0710_1272_amd import lbmd as B
+    ora = oracle_sim(rep, md, rho, u, beads=beads, step0=7)
+    u_o, node_o = O.interp(box, ora.f, ora.r)
+    F0, _ = O.conservative_forces(box, md, chains, beads)
+    assert np.max(np.abs(F0)) > 0.5, "the configuration must have active contacts"
+    r_o, v_o = ora.r.copy(), ora.v.copy()
+    fbar_o, flags_o = O.md_substeps(box, md, chains, r_o, v_o, u_o, 7, rep.seed)
+    with gpu_sim([rep], md, storage, rho, u, beads=beads, step0=7) as sim:
+        sim.couple(B.LB_COUPLE_INTERP)
+        sim.md_step()
+        r_g, v_g = sim.beads()
+        u_g, fb_g, node_g = sim.coupling()
+        word, _ = sim.status()
+    log(f"  dense md ({'periodic' if periodic else 'pore'}, storage {storage}): "
+        f"|dr| {np.max(np.abs(r_g - r_o)):.2e} |dv| {np.max(np.abs(v_g - v_o)):.2e} "
+        f"|dFbar| {np.max(np.abs(fb_g - fbar_o)):.2e} max|v| {np.max(np.abs(v_o)):.2e}")
+    assert word == flags_o == 0
+    assert np.array_equal(node_g, node_o)
+    assert np.max(np.abs(u_g - u_o)) < tol
+    scale_v = max(1.0, np.max(np.abs(v_o)))
+    assert np.max(np.abs(r_g - r_o)) < tol
+    assert np.max(np.abs(v_g - v_o)) < tol * scale_v
+    assert np.max(np.abs(fb_g - fbar_o)) < tol * scale_v
+
+
+@pytest.mark.parametrize("storage,tol", [(F64, 1e-12), (F32, 1e-5)], ids=["f64", "f32"])
+def test_two_beads_on_one_node_spread(storage, tol):
+    """Beads 0 and 1 (bonded, 1.2 apart along the cell diagonal) share node (6,6,6):
+    the reaction spread there is the sum of both beads' Fbar."""
+    box = Box(12, 12, 12, (PERIODIC,) * 3, (), 1.0)
+    md = MDParams(f_drive=0.0)
+    beads = np.array([[5.6, 5.6, 5.6], [5.6 + 1.2 / np.sqrt(3)] * 3, [7.4, 6.3, 6.3]])
+    rep = Replica(box, [3], 9)
+    rho, u = G.random_small_flow(box, 3, du=0.01)
+    ora = oracle_sim(rep, md, rho, u, beads=beads)
+    _, node0 = O.interp(box, ora.f, ora.r)
+    assert node0[0] == node0[1] != node0[2]
+    ora.step(2)
+    with gpu_sim([rep], md, storage, rho, u, beads=beads) as sim:
+        sim.step(2)
+        f = sim.populations()
+        r, _ = sim.beads()
+    assert max_rel(f, ora.f, _fluid(box)) < tol
+    assert np.max(np.abs(r - ora.r)) < 1e3 * tol
