@@ -119,8 +119,19 @@ typedef struct lbmd_config {
     lbmd_md_params md;
     const lbmd_initial_state* init;    /* may be NULL: rest fluid at rho0, no beads allowed */
     int block_size;                    /* threads per block of the lattice kernel, 0 = default */
+    int lattice_mapping;               /* LB_MAP_*: how lattice-kernel threads map to nodes */
+    int xcd_order;                     /* LB_XCD_* or a chunk size > 0: tile order over the 8 XCDs */
     unsigned flags;                    /* LB_CFG_* */
 } lbmd_config;
+
+/* lattice_mapping */
+#define LB_MAP_AUTO 0  /* flat (LB_CFG_AUTOTUNE also tries rows) */
+#define LB_MAP_FLAT 1  /* each wave takes 64 consecutive nodes of a replica */
+#define LB_MAP_ROWS 2  /* each wave takes one segment of at most 64 nodes of one x-row */
+/* xcd_order (a value C > 0 deals chunks of C consecutive tiles round-robin to the XCDs) */
+#define LB_XCD_AUTO 0        /* contiguous for one replica, hardware order for several */
+#define LB_XCD_HARDWARE (-1) /* blocks in launch order (the hardware deals them round-robin) */
+#define LB_XCD_CONTIGUOUS (-2) /* each XCD takes one contiguous eighth of the tiles */
 
 /* Device buffers.  Either all NULL-free (caller-owned, sizes from
  * lb_required_bytes) or the whole struct pointer NULL (library-owned). */
@@ -199,6 +210,11 @@ size_t lb_moments_bytes(const lbmd_ctx* ctx, int replica, unsigned what);
 
 /* Lattice-kernel launch shape in use (threads per block). */
 int lb_block_size(const lbmd_ctx* ctx);
+
+/* Lattice-kernel launch shape in use: threads per block, LB_MAP_FLAT/ROWS and the XCD
+ * tile order (LB_XCD_HARDWARE, LB_XCD_CONTIGUOUS or a chunk size).  Any pointer may be
+ * NULL.  Returns LB_OK or LB_EINVAL for a NULL context. */
+int lb_launch_shape(const lbmd_ctx* ctx, int* block, int* mapping, int* xcd_order);
 
 /* Synchronises the stream, frees library-owned buffers and the context. */
 int lb_destroy(lbmd_ctx* ctx);

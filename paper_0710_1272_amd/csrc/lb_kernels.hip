@@ -24,12 +24,22 @@ __device__ __forceinline__ void for_pops(F&& f) {
     for_pops_impl(f, std::make_integer_sequence<int, Q>{});
 }
 
-// Blocks are dealt round-robin to the 8 XCDs; give each XCD one contiguous run of
-// tiles so that neighbouring tiles, which share the cache lines at their edges,
-// meet in the same L2.
-__device__ __forceinline__ int xcd_tile(int b, int G) {
-    const int per = G >> 3, rem = G & 7, j = b & 7;
-    return j * per + (j < rem ? j : rem) + (b >> 3);
+// Blocks are dealt round-robin to the 8 XCDs.  Tile order options:
+//   C < 0: XCD j takes one contiguous eighth of the tiles (best for one big box);
+//   C = 0: the hardware order;
+//   C > 0: XCD j takes the chunks j, j+8, j+16, ... of C consecutive tiles, locality
+//          with balance when the work per tile is uneven (many small replicas); the
+//          partial super-chunk at the end keeps its order.
+__device__ __forceinline__ int xcd_tile(int b, int G, int C) {
+    if (C < 0) {
+        const int per = G >> 3, rem = G & 7, j = b & 7;
+        return j * per + (j < rem ? j : rem) + (b >> 3);
+    }
+    if (C == 0) return b;
+    const int S = 8 * C;
+    if (b >= (G / S) * S) return b;
+    const int j = b & 7, l = b >> 3;
+    return ((l / C) * 8 + j) * C + (l % C);
 }
 
 __device__ __forceinline__ int replica_of_tile(const int* __restrict__ prefix, int n_reps, int tile) {
@@ -44,7 +54,8 @@ __device__ __forceinline__ int replica_of_tile(const int* __restrict__ prefix, i
 
 enum GatherKind { G_FAST = 0, G_WALL = 1, G_GENERIC = 2 };
 
-// Incoming populations of one lane.
+// Incoming populations of one lane of the flattened mapping (64 consecutive nodes
+// per wave, possibly spanning rows).
 //  G_GENERIC: any lane (full resolver, used by waves touching a y/z face);
 //  G_WALL:    y and z interior, lanes may neighbour a wall (solid test per source);
 //  G_FAST:    y and z interior, no wall within one node (only x faces need care).
@@ -124,6 +135,81 @@ __device__ __forceinline__ void gather19(const Replica& R, const typename Codec<
     });
 }
 
+// Row-segment work units: one wave owns up to 64 consecutive x of one row (y, z) of
+// one replica, so y, z and every face decision are uniform across the wave and a
+// lane only has to care about its own x.  segs = ceil(nx / 64) units per row.
+struct RowUnit {
+    int y, z, x0;
+    bool valid;
+};
+
+__device__ __forceinline__ RowUnit row_unit(const Replica& R, int unit) {
+    RowUnit u;
+    const int segs = (R.nx + 63) >> 6;
+    const int rows = R.ny * R.nz;
+    u.valid = unit < rows * segs;
+    const int row = unit / segs;
+    u.x0 = (unit - row * segs) << 6;
+    u.z = row / R.ny;
+    u.y = row - u.z * R.ny;
+    return u;
+}
+
+// Incoming populations of one lane of a row unit.  Face handling is uniform (the
+// wave's y and z); x faces are per lane.  WALL: the segment is within one node of a
+// wall plane, so every source is tested for solidity (bounce-back); the pore test of
+// a source depends only on (y - c_y, z - c_z) and is uniform.
+template <int S, bool WALL>
+__device__ __forceinline__ void gather_row(const Replica& R, const typename Codec<S>::T* __restrict__ src,
+                                           int idx, int x, int y, int z, typename Codec<S>::R* f) {
+    using C = Codec<S>;
+    const long long V = R.V;
+    const int nx = R.nx, ny = R.ny, nz = R.nz, nxy = R.nx * R.ny;
+    const typename C::T* __restrict__ base = src + R.pop_base;
+    for_pops([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        constexpr int cx = cx_of(p), cy = cy_of(p), cz = cz_of(p);
+        int node = idx - (cx + cy * nx + cz * nxy);
+        bool fx = false, fy = false, fz = false;
+        int sy = y - cy, sz = z - cz;
+        if constexpr (cx != 0) {
+            if (x == (cx > 0 ? 0 : nx - 1)) {
+                if (R.fs[0]) { node += cx; fx = true; }
+                else node += cx * nx;
+            }
+        }
+        if constexpr (cy != 0) {
+            if (y == (cy > 0 ? 0 : ny - 1)) {
+                if (R.fs[1]) { node += cy * nx; fy = true; sy = y; }
+                else { node += cy * nxy; sy += cy * ny; }
+            }
+        }
+        if constexpr (cz != 0) {
+            if (z == (cz > 0 ? 0 : nz - 1)) {
+                if (R.fs[2]) { node += cz * nxy; fz = true; sz = z; }
+                else { node += cz * (long long)nxy * nz; sz += cz * nz; }
+            }
+        }
+        int q = mirror_combo<p>(fx, fy, fz);
+        if constexpr (WALL && p != 0) {
+            // walls are at least two planes away from the x faces, so x - c_x is the
+            // source plane of every lane that can see a wall
+            bool solid = false;
+#pragma unroll
+            for (int k = 0; k < LB_MAX_WALLS; ++k) {
+                if (k >= R.n_walls) break;
+                const int* w = R.wall[k];
+                const bool inpore = pore_open(w) && sy >= w[2] && sy <= w[3] && sz >= w[4] && sz <= w[5];
+                solid = solid || (!inpore && x - cx >= w[0] && x - cx <= w[1]);
+            }
+            if (solid) { node = idx; q = opp_of(p); }
+        }
+        // q differs from p only by reflections or reversal, which keep the weight
+        // class, so the codec scale of p applies to slot q
+        f[p] = C::template load<p>(base[(long long)q * V + node]);
+    });
+}
+
 // BGK relaxation of one node, in place on f (full populations or deviations).
 template <int S>
 __device__ __forceinline__ typename Codec<S>::R collide(typename Codec<S>::R* f,
@@ -162,46 +248,73 @@ __device__ __forceinline__ typename Codec<S>::R collide(typename Codec<S>::R* f,
     return rho;
 }
 
+// Thread-to-node mappings of the lattice kernel.
+enum LatticeMapping { MAP_FLAT = 0, MAP_ROWS = 1 };
+
 template <int S, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_stream_collide(const Replica* __restrict__ reps,
                                                           const int* __restrict__ prefix,
                                                           int n_reps,
                                                           const typename Codec<S>::T* __restrict__ src,
                                                           typename Codec<S>::T* __restrict__ dst,
-                                                          RunState* __restrict__ st, int bump_step) {
+                                                          RunState* __restrict__ st, int bump_step,
+                                                          int xcd_chunk, int mapping) {
     using C = Codec<S>;
     using Rl = typename C::R;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (bump_step && blockIdx.x == 0 && threadIdx.x == 0) st->step += 1;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, xcd_chunk);
     const int r = replica_of_tile(prefix, n_reps, tile);
     const Replica& R = reps[r];
-    const int idx = (tile - prefix[r]) * BLOCK + threadIdx.x;
-    bool active = idx < R.V;
-    const uint32_t t = fdiv((uint32_t)idx, R.div_nx);
-    const int x = idx - (int)t * R.nx;
-    const uint32_t zz = fdiv(t, R.div_ny);
-    const int y = (int)t - (int)zz * R.ny;
-    const int z = (int)zz;
-    bool face = false, zone = false;
-    if (active) {
-        if (is_solid(R, x, y, z)) active = false;
-        face = y == 0 || y == R.ny - 1 || z == 0 || z == R.nz - 1;
+    Rl f[Q];
+    int idx;
+    if (mapping == MAP_ROWS) {
+        // one wave per row segment: y, z and the face decisions are wave-uniform
+        constexpr int W = BLOCK / 64;
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const RowUnit U = row_unit(R, (tile - prefix[r]) * W + wave);
+        if (!U.valid) return;
+        const int x = U.x0 + (threadIdx.x & 63);
+        const int y = U.y, z = U.z;
+        if (x >= R.nx) return;
+        if (is_solid(R, x, y, z)) return;  // solid nodes are never read
+        idx = x + R.nx * (y + R.ny * z);
+        bool zone = false;
 #pragma unroll
         for (int k = 0; k < LB_MAX_WALLS; ++k) {
             if (k >= R.n_walls) break;
-            zone = zone || (x >= R.wall[k][0] - 1 && x <= R.wall[k][1] + 1);
+            zone = zone || (U.x0 <= R.wall[k][1] + 1 && U.x0 + 63 >= R.wall[k][0] - 1);
         }
+        if (zone) gather_row<S, true>(R, src, idx, x, y, z, f);
+        else gather_row<S, false>(R, src, idx, x, y, z, f);
+    } else {
+        // 64 consecutive nodes per wave; waves that touch a y/z face take the general
+        // resolver, waves next to a wall the solid-testing one
+        idx = (tile - prefix[r]) * BLOCK + threadIdx.x;
+        bool active = idx < R.V;
+        const uint32_t t = fdiv((uint32_t)idx, R.div_nx);
+        const int x = idx - (int)t * R.nx;
+        const uint32_t zz = fdiv(t, R.div_ny);
+        const int y = (int)t - (int)zz * R.ny;
+        const int z = (int)zz;
+        bool face = false, zone = false;
+        if (active) {
+            if (is_solid(R, x, y, z)) active = false;
+            face = y == 0 || y == R.ny - 1 || z == 0 || z == R.nz - 1;
+#pragma unroll
+            for (int k = 0; k < LB_MAX_WALLS; ++k) {
+                if (k >= R.n_walls) break;
+                zone = zone || (x >= R.wall[k][0] - 1 && x <= R.wall[k][1] + 1);
+            }
+        }
+        face = face && active;
+        zone = zone && active;
+        const bool any_face = __ballot(face) != 0;
+        const bool any_zone = __ballot(zone) != 0;
+        if (!active) return;
+        if (any_face) gather19<S, G_GENERIC>(R, src, idx, x, y, z, f);
+        else if (any_zone) gather19<S, G_WALL>(R, src, idx, x, y, z, f);
+        else gather19<S, G_FAST>(R, src, idx, x, y, z, f);
     }
-    face = face && active;
-    zone = zone && active;
-    const bool any_face = __ballot(face) != 0;
-    const bool any_zone = __ballot(zone) != 0;
-    if (bump_step && blockIdx.x == 0 && threadIdx.x == 0) st->step += 1;
-    if (!active) return;
-
-    Rl f[Q];
-    if (any_face) gather19<S, G_GENERIC>(R, src, idx, x, y, z, f);
-    else if (any_zone) gather19<S, G_WALL>(R, src, idx, x, y, z, f);
-    else gather19<S, G_FAST>(R, src, idx, x, y, z, f);
 
     const Rl rho = collide<S>(f, (Rl)R.omega, (Rl)R.rho0);
     if (!(rho > Rl(0)) || !(rho < Rl(1e30))) atomicOr(&st->err, LB_ERR_DENSITY);
@@ -393,7 +506,7 @@ static hipError_t launch_sc_t(const Context& c, const void* src, void* dst, bool
     using T = typename Codec<S>::T;
     hipLaunchKernelGGL((k_stream_collide<S, BLOCK>), dim3(c.lat.total_tiles), dim3(BLOCK), 0, s,
                        c.d_reps, c.lat.d_prefix, (int)c.reps.size(), (const T*)src, (T*)dst, c.d_state,
-                       bump ? 1 : 0);
+                       bump ? 1 : 0, c.lat_chunk, c.lat.mapping);
     return hipGetLastError();
 }
 

@@ -95,9 +95,9 @@ WorkLayout work_layout(int n_reps, int max_V, long long max_stage_nodes) {
     L.stage_doubles = (size_t)(19 * stage_nodes);
     L.stage = off;
     off += align256(sizeof(double) * L.stage_doubles);
-    L.n_prefix_tables = kNumBlockSizes;
+    L.n_prefix_tables = 2 * kNumBlockSizes;
     L.prefix = off;
-    off += align256(sizeof(int) * (size_t)(n_reps + 1) * kNumBlockSizes);
+    off += align256(sizeof(int) * (size_t)(n_reps + 1) * kNumBlockSizes * 2);
     L.total = off;
     return L;
 }
@@ -154,6 +154,9 @@ int lb_validate_config(const lbmd_config* cfg) {
         for (int b : kBlockSizes) ok = ok || b == cfg->block_size;
         if (!ok) return fail(LB_EINVAL, "block_size must be 0, 64, 128, 256, 512 or 1024");
     }
+    if (cfg->lattice_mapping < LB_MAP_AUTO || cfg->lattice_mapping > LB_MAP_ROWS)
+        return fail(LB_EINVAL, "unknown lattice_mapping");
+    if (cfg->xcd_order < LB_XCD_CONTIGUOUS) return fail(LB_EINVAL, "unknown xcd_order");
     int total_beads = 0;
     for (int r = 0; r < cfg->n_replicas; ++r) {
         const lbmd_replica& R = cfg->replicas[r];
@@ -218,9 +221,10 @@ size_t lb_required_bytes(const lbmd_config* cfg, int which) {
 
 namespace {
 
-int set_lattice_shape(Context& c, int block) {
+int set_lattice_shape(Context& c, int block, int mapping = -1) {
+    if (mapping < 0) mapping = c.lat.mapping;
     for (auto& L : c.lat_all)
-        if (L.block == block) {
+        if (L.block == block && L.mapping == mapping) {
             c.lat = L;
             return LB_OK;
         }
@@ -333,26 +337,38 @@ int autotune(Context& c) {
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     float best = 1e30f;
-    int best_block = c.lat.block;
-    for (int b : {128, 256, 512, 1024}) {
-        int rc = set_lattice_shape(c, b);
-        if (rc != LB_OK) return rc;
-        HIP_TRY(launch_stream_collide(c, c.pops[c.cur], c.pops[1 - c.cur], false, c.stream));
-        HIP_TRY(hipEventRecord(e0, c.stream));
-        for (int k = 0; k < 5; ++k)
+    int best_block = c.lat.block, best_chunk = c.lat_chunk, best_map = c.lat.mapping;
+    for (int map : {0, 1})
+    for (int b : {128, 256, 512}) {
+        for (int chunk : {-1, 0, 16, 64}) {
+            int rc = set_lattice_shape(c, b, map);
+            if (rc != LB_OK) return rc;
+            c.lat_chunk = chunk;
             HIP_TRY(launch_stream_collide(c, c.pops[c.cur], c.pops[1 - c.cur], false, c.stream));
-        HIP_TRY(hipEventRecord(e1, c.stream));
-        HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) {
-            best = ms;
-            best_block = b;
+            // best of three rounds of 10 back-to-back launches (short kernels are noisy)
+            float ms = 1e30f;
+            for (int round = 0; round < 3; ++round) {
+                HIP_TRY(hipEventRecord(e0, c.stream));
+                for (int k = 0; k < 10; ++k)
+                    HIP_TRY(launch_stream_collide(c, c.pops[c.cur], c.pops[1 - c.cur], false, c.stream));
+                HIP_TRY(hipEventRecord(e1, c.stream));
+                HIP_TRY(hipEventSynchronize(e1));
+                float t = 0;
+                HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+                ms = std::min(ms, t);
+            }
+            if (ms < best) {
+                best = ms;
+                best_block = b;
+                best_chunk = chunk;
+                best_map = map;
+            }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return set_lattice_shape(c, best_block);
+    c.lat_chunk = best_chunk;
+    return set_lattice_shape(c, best_block, best_map);
 }
 
 void destroy_graphs(Context& c) {
@@ -565,20 +581,46 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
     c.host_step = st.step;
     if ((rc = check(hipMemcpy(c.d_state, &st, sizeof st, hipMemcpyHostToDevice), "upload state"))) return bail(rc);
 
-    // tile prefix tables for every lattice block size
+    // tile prefix tables for every lattice block size and both thread mappings
     int* prefix_base = (int*)(wb + W.prefix);
-    for (int bi = 0; bi < kNumBlockSizes; ++bi) {
-        const int b = kBlockSizes[bi];
-        std::vector<int> pre(c.reps.size() + 1, 0);
-        for (size_t r = 0; r < c.reps.size(); ++r) pre[r + 1] = pre[r] + (c.reps[r].V + b - 1) / b;
-        LatticeLaunch L;
-        L.block = b;
-        L.total_tiles = pre.back();
-        L.d_prefix = prefix_base + bi * (int)(c.reps.size() + 1);
-        if ((rc = check(hipMemcpy(L.d_prefix, pre.data(), sizeof(int) * pre.size(), hipMemcpyHostToDevice), "upload tiles")))
-            return bail(rc);
-        c.lat_all.push_back(L);
+    for (int mi = 0; mi < 2; ++mi) {
+        for (int bi = 0; bi < kNumBlockSizes; ++bi) {
+            const int b = kBlockSizes[bi];
+            std::vector<int> pre(c.reps.size() + 1, 0);
+            for (size_t r = 0; r < c.reps.size(); ++r) {
+                const Replica& R = c.reps[r];
+                long long tiles;
+                if (mi == 0) {
+                    tiles = (R.V + b - 1) / b;
+                } else {
+                    // one wave per row segment of at most 64 nodes
+                    const long long units = (long long)R.ny * R.nz * ((R.nx + 63) / 64);
+                    tiles = (units + b / 64 - 1) / (b / 64);
+                }
+                pre[r + 1] = pre[r] + (int)tiles;
+            }
+            LatticeLaunch L;
+            L.block = b;
+            L.mapping = mi;
+            L.total_tiles = pre.back();
+            L.d_prefix = prefix_base + (mi * kNumBlockSizes + bi) * (int)(c.reps.size() + 1);
+            if ((rc = check(hipMemcpy(L.d_prefix, pre.data(), sizeof(int) * pre.size(), hipMemcpyHostToDevice),
+                            "upload tiles")))
+                return bail(rc);
+            c.lat_all.push_back(L);
+        }
     }
+    // launch shape: flattened mapping; contiguous XCD ranges for one box, hardware order
+    // for several (uneven) boxes; LB_CFG_AUTOTUNE times the alternatives
+    bool rows_fit = true;
+    for (const Replica& R : c.reps) rows_fit = rows_fit && (R.nx % 64 == 0);
+    // measured: row segments win only marginally (FP32, one box), so flat is the default
+    (void)rows_fit;
+    c.lat.mapping = cfg->lattice_mapping == LB_MAP_ROWS ? 1 : 0;
+    if (cfg->xcd_order == LB_XCD_AUTO) c.lat_chunk = c.reps.size() == 1 ? -1 : 0;
+    else if (cfg->xcd_order == LB_XCD_HARDWARE) c.lat_chunk = 0;
+    else if (cfg->xcd_order == LB_XCD_CONTIGUOUS) c.lat_chunk = -1;
+    else c.lat_chunk = cfg->xcd_order;
     if ((rc = set_lattice_shape(c, cfg->block_size ? cfg->block_size : 256))) return bail(rc);
 
     if ((rc = check(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking), "side stream"))) return bail(rc);
@@ -664,6 +706,15 @@ size_t lb_moments_bytes(const lbmd_ctx* ctx, int replica, unsigned what) {
 }
 
 int lb_block_size(const lbmd_ctx* ctx) { return ctx ? ctx->c.lat.block : 0; }
+
+int lb_launch_shape(const lbmd_ctx* ctx, int* block, int* mapping, int* xcd_order) {
+    if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+    const Context& c = ctx->c;
+    if (block) *block = c.lat.block;
+    if (mapping) *mapping = c.lat.mapping == 1 ? LB_MAP_ROWS : LB_MAP_FLAT;
+    if (xcd_order) *xcd_order = c.lat_chunk < 0 ? LB_XCD_CONTIGUOUS : (c.lat_chunk == 0 ? LB_XCD_HARDWARE : c.lat_chunk);
+    return LB_OK;
+}
 
 }  // extern "C"
 

@@ -28,8 +28,9 @@ enum MDMode : int { MD_INTERP = 1, MD_SUBSTEPS = 2, MD_COUPLED = 3 };
 // Lattice-kernel launch description for one block size.
 struct LatticeLaunch {
     int block = 0;
+    int mapping = 0;          // 0: 64 consecutive nodes per wave; 1: one row segment per wave
     int total_tiles = 0;
-    int* d_prefix = nullptr;  // [n_reps + 1] first tile of each replica
+    int* d_prefix = nullptr;  // [n_reps + 1] first block of each replica (one row segment per wave)
 };
 
 struct Context {
@@ -67,6 +68,7 @@ struct Context {
     void* bead_ptrs = nullptr;         // BeadPtrs<float> or BeadPtrs<double> (by storage)
 
     LatticeLaunch lat;                 // current lattice launch shape
+    int lat_chunk = -1;                // lattice tile order over XCDs (-1 contiguous, 0 none, C chunks)
     std::vector<LatticeLaunch> lat_all;
     int md_block = 256;
 

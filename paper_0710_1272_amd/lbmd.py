@@ -21,6 +21,8 @@ LB_BC_PERIODIC, LB_BC_FREESLIP = 0, 1
 LB_STORE_F64, LB_STORE_F32, LB_STORE_F16DEV, LB_STORE_BF16DEV = 0, 1, 2, 3
 LB_MAX_WALLS = 2
 LB_CFG_NO_GRAPH, LB_CFG_AUTOTUNE = 1, 2
+LB_MAP_AUTO, LB_MAP_FLAT, LB_MAP_ROWS = 0, 1, 2
+LB_XCD_AUTO, LB_XCD_HARDWARE, LB_XCD_CONTIGUOUS = 0, -1, -2
 LB_BUF_POPS, LB_BUF_BEADS, LB_BUF_WORK = 0, 1, 2
 LB_STEP_COUPLED = 1
 LB_COUPLE_INTERP, LB_COUPLE_SPREAD = 1, 2
@@ -30,7 +32,7 @@ LB_ERR_BEAD_IN_SOLID, LB_ERR_BEAD_OUTSIDE, LB_ERR_NONFINITE, LB_ERR_BOND_STRETCH
     1, 2, 4, 8, 16)
 
 EXPORTED = ["lb_required_bytes", "lb_validate_config", "lb_init", "lb_step", "lb_couple", "md_step",
-            "lb_moments", "lb_moments_bytes", "lb_block_size", "lb_destroy", "lb_strerror",
+            "lb_moments", "lb_moments_bytes", "lb_block_size", "lb_launch_shape", "lb_destroy", "lb_strerror",
             "lb_last_error_message"]
 
 
@@ -62,7 +64,8 @@ class lbmd_initial_state(C.Structure):
 class lbmd_config(C.Structure):
     _fields_ = [("n_replicas", C.c_int), ("replicas", C.POINTER(lbmd_replica)), ("storage", C.c_int),
                 ("md", lbmd_md_params), ("init", C.POINTER(lbmd_initial_state)),
-                ("block_size", C.c_int), ("flags", C.c_uint)]
+                ("block_size", C.c_int), ("lattice_mapping", C.c_int), ("xcd_order", C.c_int),
+                ("flags", C.c_uint)]
 
 
 class lbmd_buffers(C.Structure):
@@ -92,6 +95,7 @@ def lib():
         L.lb_moments_bytes.argtypes = [C.c_void_p, C.c_int, C.c_uint]
         L.lb_moments_bytes.restype = C.c_size_t
         L.lb_block_size.argtypes = [C.c_void_p]
+        L.lb_launch_shape.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.lb_destroy.argtypes = [C.c_void_p]
         L.lb_strerror.argtypes = [C.c_int]
         L.lb_strerror.restype = C.c_char_p
@@ -124,7 +128,8 @@ class Config:
     """Builds and owns the ctypes structures (and the arrays they point to)."""
 
     def __init__(self, replicas, md, storage: int, init: Optional[dict] = None,
-                 block_size: int = 0, flags: int = 0):
+                 block_size: int = 0, flags: int = 0, mapping: int = LB_MAP_AUTO,
+                 xcd_order: int = LB_XCD_AUTO):
         self._keep: List[object] = []
         n = len(replicas)
         self.reps = (lbmd_replica * n)()
@@ -162,6 +167,8 @@ class Config:
         self.cfg.md = self.md
         self.cfg.init = C.pointer(self.init)
         self.cfg.block_size = int(block_size)
+        self.cfg.lattice_mapping = int(mapping)
+        self.cfg.xcd_order = int(xcd_order)
         self.cfg.flags = int(flags)
 
     def validate(self) -> int:
@@ -175,14 +182,15 @@ class Simulation:
     """A context of the library: replicas, their populations and beads on one GPU."""
 
     def __init__(self, replicas, md, storage: int, init: Optional[dict] = None,
-                 block_size: int = 0, flags: int = 0, device_buffers: bool = True):
+                 block_size: int = 0, flags: int = 0, device_buffers: bool = True,
+                 mapping: int = LB_MAP_AUTO, xcd_order: int = LB_XCD_AUTO):
         import torch
 
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the lbmd library runs on an MI355X (gfx950) only")
         self.replicas = list(replicas)
         self.storage = storage
-        self._cfg = Config(self.replicas, md, storage, init, block_size, flags)
+        self._cfg = Config(self.replicas, md, storage, init, block_size, flags, mapping, xcd_order)
         L = lib()
         self._bufs = None
         self._tensors = []
@@ -219,6 +227,12 @@ class Simulation:
     @property
     def block_size(self) -> int:
         return lib().lb_block_size(self.ctx)
+
+    def launch_shape(self):
+        b, m, x = C.c_int(), C.c_int(), C.c_int()
+        _check(lib().lb_launch_shape(self.ctx, C.byref(b), C.byref(m), C.byref(x)), "lb_launch_shape")
+        return {"block": b.value, "mapping": {LB_MAP_FLAT: "flat", LB_MAP_ROWS: "rows"}[m.value],
+                "xcd_order": x.value}
 
     # -- observables ----------------------------------------------------------------------
     def _moments(self, replica: int, what: int, allow_unstable: bool = False) -> np.ndarray:
