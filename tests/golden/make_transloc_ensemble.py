@@ -1,0 +1,80 @@
+"""Writes the oracle's ensemble of translocation times used by the distributional GPU test.
+
+Every event is one replica of the 48^3 pore box of workloads.configs.ensemble48_n32 (the
+translocation set-up of Sec. III at a reduced size): a 32-bead chain grown from the pore mouth
+with its own seed, advanced by FP64 coupled oracle steps until every bead lies past the wall's
+mid-plane (the completion step t_done) or the step cap is reached (t_done = -1, censored).
+Only oracle/ and the seeded input generators of workloads/ are called.
+
+    python tests/golden/make_transloc_ensemble.py --events 256 --jobs 8
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "transloc_pore48_n32.txt")
+CHUNK = 50
+
+
+def _event(k: int):
+    os.environ["OMP_NUM_THREADS"] = "1"
+    import numpy as np
+
+    from oracle import oracle as O
+    from workloads import configs as WC
+    from workloads import generate as G
+
+    w = WC.ensemble48_n32(k + 1, WC.ENSEMBLE_SEED_ORACLE)
+    rep = w.replicas[k]
+    beads = G.replica_beads(rep, w.md)
+    f0 = O.equilibrium_populations(rep.box, np.full(rep.box.nodes, rep.box.rho0),
+                                   np.zeros((3, rep.box.nodes)))
+    sim = O.Sim(rep.box, w.md, rep.chain_len, f0, beads, None, seed=rep.seed)
+    while sim.t_done < 0 and sim.step_no < WC.ENSEMBLE_STEP_CAP:
+        sim.step(min(CHUNK, WC.ENSEMBLE_STEP_CAP - sim.step_no))
+    return rep.seed, sim.t_done, sim.flags
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--events", type=int, default=256)
+    ap.add_argument("--jobs", type=int, default=8)
+    args = ap.parse_args()
+    from multiprocessing import get_context
+
+    from workloads import configs as WC
+
+    t0 = time.time()
+    rows = []
+    with get_context("spawn").Pool(args.jobs) as pool:
+        for i, row in enumerate(pool.imap(_event, range(args.events))):
+            rows.append(row)
+            print(f"event {i}: seed {row[0]} t_done {row[1]} flags {row[2]} "
+                  f"({time.time() - t0:.0f} s)", flush=True)
+    md = WC.MDParams()
+    with open(OUT, "w") as fh:
+        fh.write("# Translocation times of the FP64 oracle (coupled LB + bead steps, Sec. II-III).\n")
+        fh.write("# Written by tests/golden/make_transloc_ensemble.py; inputs from workloads.configs."
+                 "ensemble48_n32.\n")
+        fh.write("# box 48^3, free-slip faces, tau=1, one wall x=22..24 with pore y,z=23..25; "
+                 "one chain of 32 beads from the pore mouth\n")
+        fh.write(f"# M={md.M} mass={md.mass} gamma={md.gamma} kT={md.kT} k_bond={md.k_bond} "
+                 f"r0={md.r0} eps={md.eps} sigma={md.sigma} eps_w={md.eps_w} sigma_w={md.sigma_w} "
+                 f"f_drive={md.f_drive}\n")
+        fh.write(f"# seeds {WC.ENSEMBLE_SEED_ORACLE}+k; step cap {WC.ENSEMBLE_STEP_CAP}; "
+                 "t_done = -1 marks a censored event\n")
+        fh.write("# seed t_done flags\n")
+        for seed, t, fl in rows:
+            fh.write(f"{seed} {t} {fl}\n")
+    print(f"wrote {OUT}: {len(rows)} events in {time.time() - t0:.0f} s")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,78 @@
+"""Distributional parity of translocation times, GPU ensemble against the oracle's ensemble.
+
+Beyond a few tens of LB steps the coupled bead dynamics is chaotic (a 1e-12 perturbation
+reaches the size of the signal within ~100 steps), so no two implementations with different
+summation orders follow the same trajectory to completion.  What both must share is the
+distribution of the completion step t_done (the first step at which every bead lies past the
+wall's mid-plane, Sec. III).  The oracle's sample (FP64, stored in tests/golden by a script
+that calls only the oracle) and the GPU's sample come from disjoint seed ranges, so they are
+independent; the test asks for a two-sample Kolmogorov-Smirnov p-value above 0.01 and means
+within three combined standard errors, for every storage format.
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+
+from tests.common import gpu_sim, log
+from workloads import configs as WC
+from workloads import generate as G
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "transloc_pore48_n32.txt")
+N_GPU = 512
+CHECK_EVERY = 250
+
+
+def oracle_times() -> np.ndarray:
+    rows = np.loadtxt(GOLDEN, comments="#", dtype=np.int64, ndmin=2)
+    assert np.all(rows[:, 2] == 0), "the oracle ensemble holds an event with error flags"
+    return rows[:, 1]
+
+
+def test_oracle_ensemble_file():
+    """The stored sample is complete, uncensored and drawn from the oracle seed range."""
+    rows = np.loadtxt(GOLDEN, comments="#", dtype=np.int64, ndmin=2)
+    assert len(rows) >= 64
+    assert np.array_equal(rows[:, 0], WC.ENSEMBLE_SEED_ORACLE + np.arange(len(rows)))
+    t = rows[:, 1]
+    assert np.all(t > 0) and np.all(t < WC.ENSEMBLE_STEP_CAP)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("storage", [WC.STORE_F64, WC.STORE_F32, WC.STORE_F16, WC.STORE_BF16],
+                         ids=["f64", "f32", "f16dev", "bf16dev"])
+def test_translocation_time_distribution(storage):
+    from scipy import stats
+
+    t_ora = oracle_times()
+    w = WC.ensemble48_n32(N_GPU, WC.ENSEMBLE_SEED_GPU, storage)
+    log(f"ensemble {w.name} storage {WC.STORE_NAMES[storage]}: {N_GPU} replicas, "
+        f"cap {WC.ENSEMBLE_STEP_CAP} steps")
+    beads = np.concatenate(G.workload_beads(w))
+    sim = gpu_sim(w.replicas, w.md, storage, beads=beads)
+    try:
+        steps = 0
+        t_gpu = np.full(N_GPU, -1)
+        while steps < WC.ENSEMBLE_STEP_CAP:
+            n = min(CHECK_EVERY, WC.ENSEMBLE_STEP_CAP - steps)
+            sim.step(n)
+            steps += n
+            t_gpu = np.array([sim.transloc(r)["t_done"] for r in range(N_GPU)])
+            log(f"  step {steps}: {int(np.sum(t_gpu >= 0))} of {N_GPU} events complete")
+            if np.all(t_gpu >= 0):
+                break
+        err, _ = sim.status()
+        assert err == 0, f"error word {err:#x}"
+    finally:
+        sim.close()
+    assert np.all(t_gpu > 0), f"{int(np.sum(t_gpu < 0))} GPU events censored at the step cap"
+    ks = stats.ks_2samp(t_gpu, t_ora)
+    m_g, m_o = t_gpu.mean(), t_ora.mean()
+    se = np.sqrt(t_gpu.var(ddof=1) / len(t_gpu) + t_ora.var(ddof=1) / len(t_ora))
+    log(f"  t_done mean gpu {m_g:.1f} (sd {t_gpu.std(ddof=1):.1f}) oracle {m_o:.1f} "
+        f"(sd {t_ora.std(ddof=1):.1f}); KS D {ks.statistic:.4f} p {ks.pvalue:.4f}; "
+        f"mean difference {abs(m_g - m_o) / se:.2f} standard errors")
+    assert ks.pvalue > 0.01
+    assert abs(m_g - m_o) < 3.0 * se

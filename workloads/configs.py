@@ -154,3 +154,20 @@ def c5_large(storage: int = STORE_F32) -> Workload:
 
 def with_storage(w: Workload, storage: int) -> Workload:
     return replace(w, storage=storage)
+
+
+# Translocation-time ensembles: independent 48^3 pore boxes, one 32-bead chain each.  The
+# oracle's ensemble and the GPU's ensemble draw from disjoint seed ranges, so the two samples
+# of completion times are independent draws of one distribution.
+ENSEMBLE_SEED_ORACLE = BASE_SEED + 100_000
+ENSEMBLE_SEED_GPU = BASE_SEED + 200_000
+ENSEMBLE_STEP_CAP = 4000
+
+
+def ensemble48_n32(n_replicas: int, seed0: int, storage: int = STORE_F32) -> Workload:
+    """n independent 48^3 boxes with one pore wall (x = 22..24) and a 32-bead chain started in
+    the pore mouth; replica k has seed seed0 + k (its chain and its random forces)."""
+    box = pore_box(48, 48, 48)
+    reps = [Replica(box, [32], seed0 + k) for k in range(n_replicas)]
+    return Workload(f"ensemble48_n32x{n_replicas}", reps, MDParams(), storage, ENSEMBLE_STEP_CAP,
+                    "48^3 boxes, 3x3 pore wall, N=32 chain each, run to completion")
