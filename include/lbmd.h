@@ -110,7 +110,9 @@ typedef struct lbmd_initial_state {
 } lbmd_initial_state;
 
 #define LB_CFG_NO_GRAPH 1u   /* enqueue plain launches instead of captured HIP graphs */
-#define LB_CFG_AUTOTUNE 2u   /* time candidate launch shapes at lb_init and keep the fastest */
+#define LB_CFG_AUTOTUNE 2u   /* time candidate launch shapes (lattice kernel, lanes per bead of
+                                the bead kernel) at lb_init and keep the fastest; the bead
+                                state is restored after the trial steps */
 
 typedef struct lbmd_config {
     int n_replicas;
@@ -121,6 +123,9 @@ typedef struct lbmd_config {
     int block_size;                    /* threads per block of the lattice kernel, 0 = default */
     int lattice_mapping;               /* LB_MAP_*: how lattice-kernel threads map to nodes */
     int xcd_order;                     /* LB_XCD_* or a chunk size > 0: tile order over the 8 XCDs */
+    int md_lanes;                      /* lanes per bead in the bead kernel: 0 = by bead count,
+                                          1, or 2/4/8/16 with lanes x (beads of the largest
+                                          replica) <= 512; LB_CFG_AUTOTUNE times the choices */
     unsigned flags;                    /* LB_CFG_* */
 } lbmd_config;
 
@@ -215,6 +220,11 @@ int lb_block_size(const lbmd_ctx* ctx);
  * tile order (LB_XCD_HARDWARE, LB_XCD_CONTIGUOUS or a chunk size).  Any pointer may be
  * NULL.  Returns LB_OK or LB_EINVAL for a NULL context. */
 int lb_launch_shape(const lbmd_ctx* ctx, int* block, int* mapping, int* xcd_order);
+
+/* Lanes per bead of the bead kernel in use (1, 2, 4, 8 or 16; each bead's neighbour
+ * loop is split over its lanes), 0 if no replica has beads, LB_EINVAL for a NULL
+ * context. */
+int lb_md_lanes(const lbmd_ctx* ctx);
 
 /* Synchronises the stream, frees library-owned buffers and the context. */
 int lb_destroy(lbmd_ctx* ctx);

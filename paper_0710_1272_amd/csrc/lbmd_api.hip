@@ -157,7 +157,7 @@ int lb_validate_config(const lbmd_config* cfg) {
     if (cfg->lattice_mapping < LB_MAP_AUTO || cfg->lattice_mapping > LB_MAP_ROWS)
         return fail(LB_EINVAL, "unknown lattice_mapping");
     if (cfg->xcd_order < LB_XCD_CONTIGUOUS) return fail(LB_EINVAL, "unknown xcd_order");
-    int total_beads = 0;
+    int total_beads = 0, max_beads = 0;
     for (int r = 0; r < cfg->n_replicas; ++r) {
         const lbmd_replica& R = cfg->replicas[r];
         const std::string at = "replica " + std::to_string(r) + ": ";
@@ -189,7 +189,10 @@ int lb_validate_config(const lbmd_config* cfg) {
             if (nb > 4096) return fail(LB_EINVAL, at + "more than 4096 beads in one replica");
         }
         total_beads += nb;
+        max_beads = std::max(max_beads, nb);
     }
+    if (cfg->md_lanes != 0 && !md_lanes_valid(cfg->md_lanes, max_beads))
+        return fail(LB_EINVAL, "md_lanes must be 0, 1, or 2/4/8/16 with md_lanes x beads per replica <= 512");
     const lbmd_md_params& m = cfg->md;
     if (total_beads > 0) {
         if (m.M < 1) return fail(LB_EINVAL, "md.M must be >= 1");
@@ -371,6 +374,69 @@ int autotune(Context& c) {
     return set_lattice_shape(c, best_block, best_map);
 }
 
+// Lanes per bead of the bead kernel: times coupled-mode launches (interpolation and M
+// substeps) for every valid choice, each from the same saved bead state, then puts the
+// bead buffer and the run state back as they were.
+int autotune_md(Context& c) {
+    if (c.ntot_beads == 0 || c.md_lanes != 0) return LB_OK;
+    std::vector<int> cand;
+    for (int G : {1, 2, 4, 8, 16})
+        if (md_lanes_valid(G, c.max_beads)) cand.push_back(G);
+    if (cand.size() < 2) return LB_OK;
+    const size_t real = c.storage == LB_STORE_F64 ? sizeof(double) : sizeof(float);
+    const size_t bytes = bead_layout(c.ntot_beads, (int)c.reps.size(), real).total;
+    void* save = nullptr;
+    HIP_TRY(hipMalloc(&save, bytes + sizeof(RunState)));
+    RunState* save_st = (RunState*)((char*)save + bytes);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = LB_OK;
+    float best = 1e30f;
+    int best_G = md_default_lanes(c.max_beads);
+    auto body = [&]() -> hipError_t {
+        hipError_t e;
+        if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
+        if ((e = hipEventCreate(&e1)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(save, c.beads, bytes, hipMemcpyDeviceToDevice, c.stream)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(save_st, c.d_state, sizeof(RunState), hipMemcpyDeviceToDevice, c.stream)) !=
+            hipSuccess)
+            return e;
+        for (int G : cand) {
+            c.md_lanes = G;
+            if ((e = hipMemcpyAsync(c.beads, save, bytes, hipMemcpyDeviceToDevice, c.stream)) != hipSuccess) return e;
+            if ((e = launch_md(c, c.pops[c.cur], MD_COUPLED, c.stream)) != hipSuccess) return e;
+            float ms = 1e30f;
+            for (int round = 0; round < 3; ++round) {
+                if ((e = hipEventRecord(e0, c.stream)) != hipSuccess) return e;
+                for (int k = 0; k < 5; ++k)
+                    if ((e = launch_md(c, c.pops[c.cur], MD_COUPLED, c.stream)) != hipSuccess) return e;
+                if ((e = hipEventRecord(e1, c.stream)) != hipSuccess) return e;
+                if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+                float t = 0;
+                if ((e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) return e;
+                ms = std::min(ms, t);
+            }
+            if (ms < best) {
+                best = ms;
+                best_G = G;
+            }
+        }
+        if ((e = hipMemcpyAsync(c.beads, save, bytes, hipMemcpyDeviceToDevice, c.stream)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(c.d_state, save_st, sizeof(RunState), hipMemcpyDeviceToDevice, c.stream)) !=
+            hipSuccess)
+            return e;
+        return hipStreamSynchronize(c.stream);
+    };
+    const hipError_t e = body();
+    if (e != hipSuccess)
+        rc = fail(e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE,
+                  std::string("bead-kernel autotune: ") + hipGetErrorString(e));
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(save);
+    c.md_lanes = best_G;
+    return rc;
+}
+
 void destroy_graphs(Context& c) {
     for (int k = 0; k < 2; ++k) {
         if (c.graph_coupled[k]) (void)hipGraphExecDestroy(c.graph_coupled[k]);
@@ -472,6 +538,7 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
     c.ntot_beads = t.beads;
     c.max_beads = t.max_beads;
     c.max_V = t.max_V;
+    c.md_lanes = cfg->md_lanes;
 
     // replica descriptors
     long long pop_base = 0;
@@ -639,6 +706,7 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
     }
     if (cfg->flags & LB_CFG_AUTOTUNE) {
         if ((rc = autotune(c))) return bail(rc);
+        if ((rc = autotune_md(c))) return bail(rc);
     }
     if ((rc = check(hipStreamSynchronize(c.stream), "sync"))) return bail(rc);
     *out = ctx;
@@ -714,6 +782,13 @@ int lb_launch_shape(const lbmd_ctx* ctx, int* block, int* mapping, int* xcd_orde
     if (mapping) *mapping = c.lat.mapping == 1 ? LB_MAP_ROWS : LB_MAP_FLAT;
     if (xcd_order) *xcd_order = c.lat_chunk < 0 ? LB_XCD_CONTIGUOUS : (c.lat_chunk == 0 ? LB_XCD_HARDWARE : c.lat_chunk);
     return LB_OK;
+}
+
+int lb_md_lanes(const lbmd_ctx* ctx) {
+    if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+    const Context& c = ctx->c;
+    if (c.ntot_beads == 0) return 0;
+    return c.md_lanes > 0 ? c.md_lanes : md_default_lanes(c.max_beads);
 }
 
 }  // extern "C"

@@ -70,7 +70,7 @@ struct Context {
     LatticeLaunch lat;                 // current lattice launch shape
     int lat_chunk = -1;                // lattice tile order over XCDs (-1 contiguous, 0 none, C chunks)
     std::vector<LatticeLaunch> lat_all;
-    int md_block = 256;
+    int md_lanes = 0;                  // lanes per bead of the bead kernel (0: by bead count)
 
     bool use_graph = true;
     hipGraphExec_t graph_coupled[2] = {nullptr, nullptr};  // by parity of cur
@@ -104,6 +104,7 @@ hipError_t launch_conserved(const Context& c, int r, const void* src, double* d_
 hipError_t launch_md(const Context& c, const void* cur, int mode, hipStream_t s);
 hipError_t launch_spread(const Context& c, void* dst, bool bump_step, hipStream_t s);
 hipError_t launch_bump(const Context& c, hipStream_t s);
-size_t md_lds_bytes(const Context& c);
+int md_default_lanes(int max_beads);
+bool md_lanes_valid(int lanes, int max_beads);
 
 }  // namespace lbmd

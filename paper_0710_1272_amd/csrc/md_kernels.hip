@@ -52,6 +52,7 @@ struct MDKArgs {
     int mode;
     int nmax;
     int list_in_lds;
+    int noise_in_lds;  // random forces of all substeps tabulated in LDS at step start
 };
 
 // nearest node: floor(r + 1/2); periodic axes wrap, free-slip axes clamp (NaN -> 0)
@@ -68,55 +69,6 @@ __device__ __forceinline__ void ngp3(const Replica& R, const double* r, int* g) 
         }
         g[a] = (int)t;
     }
-}
-
-__device__ __forceinline__ double min_image(double d, int n, int periodic) {
-    return periodic ? d - n * floor(d / n + 0.5) : d;
-}
-
-// distance to the nearest solid surface (unit cubes around solid nodes; a wall is
-// its slab minus the pore prism, as four boxes), and the vector from it to r
-__device__ inline double wall_distance(const Replica& R, const double* rin, double* dv) {
-    const int n[3] = {R.nx, R.ny, R.nz};
-    double r[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) r[a] = R.fs[a] ? rin[a] : rin[a] - n[a] * floor((rin[a] + 0.5) / n[a]);
-    double best2 = HUGE_VAL;
-    dv[0] = dv[1] = dv[2] = 0.0;
-#pragma unroll
-    for (int k = 0; k < LB_MAX_WALLS; ++k) {
-        if (k >= R.n_walls) break;
-        const int* w = R.wall[k];
-        const double X0 = w[0] - 0.5, X1 = w[1] + 0.5;
-        const bool open = pore_open(w);
-        const double Y0 = w[2] - 0.5, Y1 = w[3] + 0.5, Z0 = w[4] - 0.5, Z1 = w[5] + 0.5;
-        const int nb = open ? 4 : 1;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            if (m >= nb) break;
-            double lo[3] = {X0, -HUGE_VAL, -HUGE_VAL}, hi[3] = {X1, HUGE_VAL, HUGE_VAL};
-            if (open) {
-                if (m == 0) { hi[1] = Y0; }
-                else if (m == 1) { lo[1] = Y1; }
-                else if (m == 2) { lo[1] = Y0; hi[1] = Y1; hi[2] = Z0; }
-                else { lo[1] = Y0; hi[1] = Y1; lo[2] = Z1; }
-            }
-            double d[3], d2 = 0.0;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const double c = fmin(fmax(r[a], lo[a]), hi[a]);
-                d[a] = r[a] - c;
-                d2 += d[a] * d[a];
-            }
-            if (d2 < best2) {
-                best2 = d2;
-                dv[0] = d[0];
-                dv[1] = d[1];
-                dv[2] = d[2];
-            }
-        }
-    }
-    return sqrt(best2);
 }
 
 // The part of a replica's description the substep loop reads, copied into registers
@@ -175,9 +127,14 @@ __device__ __forceinline__ void geom_ngp(const Geom& G, const double* r, int* c)
     }
 }
 
-// distance to the nearest solid surface and the vector from it to r (see wall_distance)
+// Squared distance from r to the nearest solid surface, and the vector from that
+// surface point to r.  Solid node cubes span [i - 1/2, i + 1/2], so a wall is its slab
+// X0..X1 minus the pore prism Y0..Y1 x Z0..Z1.  Outside the prism (in y, z) the nearest
+// solid point lies straight along x, on the slab; inside it, on the nearest of the four
+// prism sides, at x clamped into the slab.  Ties go to the earlier wall and to the sides
+// in the order y-low, y-high, z-low, z-high.
 template <bool PERIODIC>
-__device__ inline double geom_wall_distance(const Geom& G, const double* rin, double* dv) {
+__device__ inline double geom_wall_dist2(const Geom& G, const double* rin, double* dv) {
     double r[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -189,34 +146,28 @@ __device__ inline double geom_wall_distance(const Geom& G, const double* rin, do
         if (k >= G.n_walls) break;
         const int* w = G.wall[k];
         const double X0 = w[0] - 0.5, X1 = w[1] + 0.5;
-        const bool open = pore_open(w);
         const double Y0 = w[2] - 0.5, Y1 = w[3] + 0.5, Z0 = w[4] - 0.5, Z1 = w[5] + 0.5;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            if (m >= (open ? 4 : 1)) break;
-            double lo[3] = {X0, -HUGE_VAL, -HUGE_VAL}, hi[3] = {X1, HUGE_VAL, HUGE_VAL};
-            if (open) {
-                if (m == 0) { hi[1] = Y0; }
-                else if (m == 1) { lo[1] = Y1; }
-                else if (m == 2) { lo[1] = Y0; hi[1] = Y1; hi[2] = Z0; }
-                else { lo[1] = Y0; hi[1] = Y1; lo[2] = Z1; }
-            }
-            double d[3], d2 = 0.0;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const double c = fmin(fmax(r[a], lo[a]), hi[a]);
-                d[a] = r[a] - c;
-                d2 += d[a] * d[a];
-            }
-            if (d2 < best2) {
-                best2 = d2;
-                dv[0] = d[0];
-                dv[1] = d[1];
-                dv[2] = d[2];
-            }
+        const double dx = r[0] - fmin(fmax(r[0], X0), X1);
+        double dy = 0.0, dz = 0.0;
+        if (pore_open(w) && r[1] >= Y0 && r[1] <= Y1 && r[2] >= Z0 && r[2] <= Z1) {
+            double side = r[1] - Y0;
+            dy = side;
+            double t = Y1 - r[1];
+            if (t < side) { side = t; dy = -t; }
+            t = r[2] - Z0;
+            if (t < side) { side = t; dy = 0.0; dz = t; }
+            t = Z1 - r[2];
+            if (t < side) { side = t; dy = 0.0; dz = -t; }
+        }
+        const double q = dx * dx + dy * dy + dz * dz;
+        if (q < best2) {
+            best2 = q;
+            dv[0] = dx;
+            dv[1] = dy;
+            dv[2] = dz;
         }
     }
-    return sqrt(best2);
+    return best2;
 }
 
 // 1/x: the hardware reciprocal in FP32 (about 1 ulp), an exact division in FP64
@@ -294,21 +245,52 @@ __device__ __forceinline__ void node_velocity(int storage, const Replica& R, con
     u[2] = j[2] / rho;
 }
 
-// sum over the G consecutive lanes of a group (G a power of two <= 64)
+// One DPP lane exchange (no LDS round trip): quad_perm [1,0,3,2] swaps neighbouring lanes,
+// [2,3,0,1] swaps lane pairs, row_half_mirror reverses each group of 8 lanes, row_mirror
+// each row of 16.
+constexpr int kDppSwap1 = 0xB1, kDppSwap2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_x(float v) {
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_x(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i<CTRL>((int)(b & 0xFFFFFFFFll));
+    const int hi = dpp_i<CTRL>((int)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_x(int v) {
+    return dpp_i<CTRL>(v);
+}
+
+// Sum over the G consecutive lanes of a group (G a power of two <= 64).  Each step adds
+// the partial sum of the partner half, so every lane of the group ends with the same
+// bits (a + b and b + a round alike): the redundant per-bead state of the group's
+// lanes stays identical.
 template <int G, class T>
 __device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-    for (int off = G / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if constexpr (G >= 2) v += dpp_x<kDppSwap1>(v);
+    if constexpr (G >= 4) v += dpp_x<kDppSwap2>(v);
+    if constexpr (G >= 8) v += dpp_x<kDppHalfMirror>(v);
+    if constexpr (G >= 16) v += dpp_x<kDppMirror>(v);
+    if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
+    if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
     return v;
 }
 
 // Pairwise separation r_i - r_j as FP32/FP64 components (minimum image on periodic
 // axes) and its square.
 template <class Real, bool PERIODIC>
-__device__ __forceinline__ Real separation(const double* ri, const double* PX, const double* PY,
-                                           const double* PZ, int j, const int* per, const double* nd,
-                                           Real* d) {
-    double dd[3] = {ri[0] - PX[j], ri[1] - PY[j], ri[2] - PZ[j]};
+__device__ __forceinline__ Real separation_v(const double* ri, const double* pj, const int* per,
+                                             const double* nd, Real* d) {
+    double dd[3] = {ri[0] - pj[0], ri[1] - pj[1], ri[2] - pj[2]};
     if constexpr (PERIODIC) {
 #pragma unroll
         for (int c = 0; c < 3; ++c)
@@ -319,6 +301,22 @@ __device__ __forceinline__ Real separation(const double* ri, const double* PX, c
     d[2] = (Real)dd[2];
     return d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
 }
+
+template <class Real, bool PERIODIC>
+__device__ __forceinline__ Real separation(const double* ri, const double* PX, const double* PY,
+                                           const double* PZ, int j, const int* per, const double* nd,
+                                           Real* d) {
+    const double pj[3] = {PX[j], PY[j], PZ[j]};
+    return separation_v<Real, PERIODIC>(ri, pj, per, nd, d);
+}
+
+// Verlet-list entries each lane keeps in registers (slot s of lane gl is entry gl + s G);
+// entries beyond them are read from the list
+// (fewer under the 1024-thread bound, where registers are scarcer)
+template <int G, int BPT, int MAXT>
+struct SlotsPerLane {
+    static constexpr int K = MAXT > 512 ? (BPT > 1 ? 1 : 2) : (BPT > 1 ? 4 : (G >= 8 ? 1 : 8 / G));
+};
 
 // Verlet list of bead i (group of G lanes): every non-bonded bead closer than the list
 // radius, in lane-then-index order.  Returns the count (may exceed the capacity).
@@ -393,6 +391,10 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
     // Verlet lists: [kNeighbourMax][nmax] in LDS when they fit, else global memory
     unsigned short* lists = a.list_in_lds ? (unsigned short*)(BN + nmax) : a.b.nlist + b0;
     const int lstride = a.list_in_lds ? nmax : NT;
+    // random forces [M][3][nmax], after the lists (or after BN when the lists are global)
+    Real* NZ = (Real*)(a.list_in_lds ? (unsigned char*)(BN + nmax) + (size_t)kNeighbourMax * nmax * 2
+                                     : (unsigned char*)(BN + nmax));
+    const bool noise_lds = G > 1 && a.noise_in_lds;
     const MDDev md = a.md;
     const int M = md.M;
     const long long step = a.st->step;
@@ -473,6 +475,9 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
     const Real eps24 = (Real)(24.0 * md.eps), sig2 = (Real)md.sigma2, rc2 = (Real)md.rc2;
     const Real epsw = (Real)md.eps_w, sigw2 = (Real)md.sigma_w2, rcw2 = (Real)md.rcw2;
     const double rcw = md.rcw;
+    // beyond this distance from a face the face WCA term is zero (a margin over the cutoff
+    // keeps the skipped terms zero under any rounding of the distance)
+    const Real rcw_gate = (Real)(md.rcw + 1e-3);
     const Real rl2 = (Real)md.rl2, hs2 = (Real)md.half_skin2;
     const Real fdrive = (Real)md.f_drive;
 
@@ -489,6 +494,19 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
         if (!own[k]) continue;
         cnt[k] = build_list<Real, G, PERIODIC>(i, n, BN[i] != 0, i > 0 && BN[i - 1] != 0, r[k], P, P + nmax,
                                                P + 2 * nmax, per, nd, rl2, gl, lists + i, lstride);
+    }
+    if (noise_lds) {
+        // the G lanes of a bead share its M Philox draws instead of each lane drawing all
+        // of them; the table is read from the next barrier on
+        const int i = grp;
+        if (own[0]) {
+            for (int s = gl; s < M; s += G) {
+                const U4 rnd = philox4x32_10(U4{(uint32_t)i, (uint32_t)step, (uint32_t)s, 1u}, seed_lo, seed_hi);
+                NZ[(3 * s + 0) * nmax + i] = A * centred_uniform<Real>(rnd.x);
+                NZ[(3 * s + 1) * nmax + i] = A * centred_uniform<Real>(rnd.y);
+                NZ[(3 * s + 2) * nmax + i] = A * centred_uniform<Real>(rnd.z);
+            }
+        }
     }
     __syncthreads();
     // Beads on one node at the start of the step are closer than sqrt(3) < rc, so they
@@ -516,6 +534,39 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
         before[k] = group_sum<G>(bf) != 0;
     }
 
+    // chain neighbours (constant over the step) and the register slots of the lists
+    bool bnk[BPT], bpk[BPT];
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+        const int i = grp + k * NG;
+        bnk[k] = own[k] && BN[i] != 0;
+        bpk[k] = own[k] && i > 0 && BN[i - 1] != 0;
+    }
+    constexpr int K = SlotsPerLane<G, BPT, MAXT>::K;
+    int slot[BPT][K], nslot[BPT];
+    auto load_slots = [&]() {
+#pragma unroll
+        for (int k = 0; k < BPT; ++k) {
+            const int i = grp + k * NG;
+            nslot[k] = 0;
+#pragma unroll
+            for (int s = 0; s < K; ++s) {
+                const int q = gl + s * G;
+                slot[k][s] = own[k] ? i : 0;  // an unused slot reads the bead itself
+                if (own[k] && cnt[k] <= kNeighbourMax && q < cnt[k]) {
+                    slot[k][s] = lists[i + q * lstride];
+                    ++nslot[k];
+                }
+            }
+        }
+    };
+    load_slots();
+    // rebuild vote: one flag per wave, double-buffered so that one barrier per substep
+    // separates the writes of a substep from its reads and from the next substep's writes
+    __shared__ int vote[2][16];
+    const int wave = tid >> 6, n_waves = (blockDim.x + 63) >> 6;
+    const bool x_periodic = PERIODIC && !GM.fs[0];
+
     for (int sub = 0; sub < M; ++sub) {
         const double* PX = P + cur * 3 * nmax;
         const double* PY = PX + nmax;
@@ -527,23 +578,33 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
             const int i = grp + k * NG;
             F[k][0] = F[k][1] = F[k][2] = 0;
             if (!own[k]) continue;
-            const bool bn = BN[i] != 0;
-            const bool bp = i > 0 && BN[i - 1] != 0;
-            // WCA against the Verlet neighbours (all pairs if the list overflowed)
+            // every position this substep reads, issued together: the register slots of
+            // the Verlet list and the two chain neighbours (the bead itself when absent)
+            double pj[K][3];
+#pragma unroll
+            for (int s = 0; s < K; ++s) {
+                const int j = slot[k][s];
+                pj[s][0] = PX[j];
+                pj[s][1] = PY[j];
+                pj[s][2] = PZ[j];
+            }
+            const int jm = bpk[k] ? i - 1 : i, jp = bnk[k] ? i + 1 : i;
+            const double pm[3] = {PX[jm], PY[jm], PZ[jm]};
+            const double pp[3] = {PX[jp], PY[jp], PZ[jp]};
+            Real noise[3];
+            if (noise_lds) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) noise[c] = NZ[(3 * sub + c) * nmax + i];
+            } else {
+                const U4 rnd = philox4x32_10(U4{(uint32_t)i, (uint32_t)step, (uint32_t)sub, 1u}, seed_lo, seed_hi);
+                noise[0] = A * centred_uniform<Real>(rnd.x);
+                noise[1] = A * centred_uniform<Real>(rnd.y);
+                noise[2] = A * centred_uniform<Real>(rnd.z);
+            }
+            // WCA against the Verlet neighbours: register slots, then any further list
+            // entries, or all pairs if the list overflowed
             Real fx = 0, fy = 0, fz = 0;
-            const bool overflow = cnt[k] > kNeighbourMax;
-            const int lim = overflow ? n : cnt[k];
-            const unsigned short* li = lists + i;
-            for (int q = gl; q < lim; q += G) {
-                int j;
-                if (overflow) {
-                    j = q;
-                    if (j == i || (j == i + 1 && bn) || (j == i - 1 && bp)) continue;
-                } else {
-                    j = li[q * lstride];
-                }
-                Real d[3];
-                const Real r2 = separation<Real, PERIODIC>(r[k], PX, PY, PZ, j, per, nd, d);
+            auto wca = [&](const Real* d, Real r2) {
                 if (r2 < rc2) {
                     const Real ir2 = fast_rcp<Real>(r2);
                     const Real s2 = sig2 * ir2;
@@ -553,6 +614,29 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
                     fy += c * d[1];
                     fz += c * d[2];
                 }
+            };
+#pragma unroll
+            for (int s = 0; s < K; ++s) {
+                if (s < nslot[k]) {
+                    Real d[3];
+                    const Real r2 = separation_v<Real, PERIODIC>(r[k], pj[s], per, nd, d);
+                    wca(d, r2);
+                }
+            }
+            const bool overflow = cnt[k] > kNeighbourMax;
+            const int lim = overflow ? n : cnt[k];
+            const unsigned short* li = lists + i;
+            for (int q = overflow ? gl : gl + K * G; q < lim; q += G) {
+                int j;
+                if (overflow) {
+                    j = q;
+                    if (j == i || (j == i + 1 && bnk[k]) || (j == i - 1 && bpk[k])) continue;
+                } else {
+                    j = li[q * lstride];
+                }
+                Real d[3];
+                const Real r2 = separation<Real, PERIODIC>(r[k], PX, PY, PZ, j, per, nd, d);
+                wca(d, r2);
             }
             F[k][0] = group_sum<G>(fx);
             F[k][1] = group_sum<G>(fy);
@@ -560,65 +644,70 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
             // harmonic bonds to the chain neighbours
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
-                const bool on = side == 0 ? bp : bn;
+                const bool on = side == 0 ? bpk[k] : bnk[k];
                 if (!on) continue;
-                const int j = side == 0 ? i - 1 : i + 1;
                 Real d[3];
-                const Real len = sqrt(separation<Real, PERIODIC>(r[k], PX, PY, PZ, j, per, nd, d));
+                const Real len = sqrt(separation_v<Real, PERIODIC>(r[k], side == 0 ? pm : pp, per, nd, d));
                 if (len > Real(2) * r0) flags |= LB_ERR_BOND_STRETCH;
                 // d points from j to i: the bond pulls i towards j when stretched
                 const Real coef = -kb * (len - r0) * fast_rcp<Real>(len);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) F[k][c] += coef * d[c];
             }
-            // nearest solid surface (only near a wall)
             if (!(isfinite(r[k][0]) && isfinite(r[k][1]) && isfinite(r[k][2]))) flags |= LB_ERR_NONFINITE;
+            // nearest solid surface and the pore drive, only within reach of a wall slab
+            // (x wrapped on a periodic axis): a bead whose nearest node is a pore node lies
+            // within half a node of its wall's slab
+            const double xw = x_periodic ? r[k][0] - nd[0] * floor((r[k][0] + 0.5) / nd[0]) : r[k][0];
             bool near_wall = false;
 #pragma unroll
             for (int w = 0; w < LB_MAX_WALLS; ++w) {
                 if (w >= GM.n_walls) break;
-                near_wall = near_wall || (r[k][0] > GM.wall[w][0] - 0.5 - rcw && r[k][0] < GM.wall[w][1] + 0.5 + rcw);
+                near_wall = near_wall || (xw > GM.wall[w][0] - 0.5 - rcw && xw < GM.wall[w][1] + 0.5 + rcw);
             }
             if (near_wall) {
                 double dv[3];
-                const double dist = geom_wall_distance<PERIODIC>(GM, r[k], dv);
-                if (dist == 0.0) {
+                const double d2w = geom_wall_dist2<PERIODIC>(GM, r[k], dv);
+                if (d2w == 0.0) {
                     flags |= LB_ERR_BEAD_IN_SOLID;
                 } else {
-                    const Real c = wca_coef<Real>((Real)(dist * dist), epsw, sigw2, rcw2);
+                    const Real c = wca_coef<Real>((Real)d2w, epsw, sigw2, rcw2);
 #pragma unroll
                     for (int q = 0; q < 3; ++q) F[k][q] += c * (Real)dv[q];
                 }
+                int g[3];
+                geom_ngp<PERIODIC>(GM, r[k], g);
+                if (geom_is_pore(GM, g)) F[k][0] += fdrive;
             }
-            // free-slip faces at -1/2 and n - 1/2
+            // free-slip faces at -1/2 and n - 1/2 (the WCA terms only within the cutoff)
+            Real dlo[3], dhi[3];
+            bool near_face = false;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
+                dlo[c] = (Real)(r[k][c] + 0.5);
+                dhi[c] = (Real)((nn[c] - 0.5) - r[k][c]);
                 if (!GM.fs[c]) continue;
-                const Real dlo = (Real)(r[k][c] + 0.5), dhi = (Real)((nn[c] - 0.5) - r[k][c]);
-                if (!(dlo > Real(0)) || !(dhi > Real(0))) {
-                    flags |= LB_ERR_BEAD_OUTSIDE;
-                    continue;
-                }
-                F[k][c] += wca_coef<Real>(dlo * dlo, epsw, sigw2, rcw2) * dlo;
-                F[k][c] -= wca_coef<Real>(dhi * dhi, epsw, sigw2, rcw2) * dhi;
+                if (!(dlo[c] > Real(0)) || !(dhi[c] > Real(0))) flags |= LB_ERR_BEAD_OUTSIDE;
+                near_face = near_face || !(dlo[c] >= rcw_gate && dhi[c] >= rcw_gate);
             }
-            // pulling force on beads whose nearest node is a pore node
-            int g[3];
-            geom_ngp<PERIODIC>(GM, r[k], g);
-            if (geom_is_pore(GM, g)) F[k][0] += fdrive;
+            if (near_face) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if (!GM.fs[c] || !(dlo[c] > Real(0)) || !(dhi[c] > Real(0))) continue;
+                    F[k][c] += wca_coef<Real>(dlo[c] * dlo[c], epsw, sigw2, rcw2) * dlo[c];
+                    F[k][c] -= wca_coef<Real>(dhi[c] * dhi[c], epsw, sigw2, rcw2) * dhi[c];
+                }
+            }
             // drag against the frozen fluid velocity and the random force
-            const U4 rnd = philox4x32_10(U4{(uint32_t)i, (uint32_t)step, (uint32_t)sub, 1u}, seed_lo, seed_hi);
-            const uint32_t rr[3] = {rnd.x, rnd.y, rnd.z};
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const Real drag = -mg * (v[k][c] - u[k][c]);
-                const Real noise = A * centred_uniform<Real>(rr[c]);
-                F[k][c] += drag + noise;
-                fb[k][c] += (drag + noise) * invM;
+                F[k][c] += drag + noise[c];
+                fb[k][c] += (drag + noise[c]) * invM;
             }
         }
         // kick-drift into the other position buffer; the single barrier below both
-        // publishes the new positions and votes on a list rebuild
+        // publishes the new positions and collects the rebuild vote
         int moved = 0;
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
@@ -638,8 +727,14 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
                 for (int c = 0; c < 3; ++c) QX[c * nmax + i] = r[k][c];
             }
         }
+        const int vb = sub & 1;
+        const bool wave_moved = __ballot(moved) != 0ull;
+        if ((tid & 63) == 0) vote[vb][wave] = wave_moved ? 1 : 0;
+        __syncthreads();
+        int any_moved = 0;
+        for (int w = 0; w < n_waves; ++w) any_moved |= vote[vb][w];
         cur ^= 1;
-        if (__syncthreads_or(moved) && sub + 1 < M) {
+        if (any_moved && sub + 1 < M) {
             ++builds;
             const double* NX = P + cur * 3 * nmax;
 #pragma unroll
@@ -648,11 +743,11 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) rref[k][c] = r[k][c];
                 if (!own[k]) continue;
-                cnt[k] = build_list<Real, G, PERIODIC>(i, n, BN[i] != 0, i > 0 && BN[i - 1] != 0, r[k], NX,
-                                                       NX + nmax, NX + 2 * nmax, per, nd, rl2, gl, lists + i,
-                                                       lstride);
+                cnt[k] = build_list<Real, G, PERIODIC>(i, n, bnk[k], bpk[k], r[k], NX, NX + nmax, NX + 2 * nmax,
+                                                       per, nd, rl2, gl, lists + i, lstride);
             }
             __syncthreads();
+            load_slots();
         }
     }
 
@@ -766,17 +861,51 @@ __global__ void k_bump(RunState* st) { st->step += 1; }
 // ---------------------------------------------------------------------------------
 static int md_nmax(const Context& c) { return (c.max_beads + 63) / 64 * 64; }
 
+static constexpr size_t kMDLdsBudget = 150 * 1024;
+
+static size_t md_base_lds(size_t nmax) { return nmax * (6 * sizeof(double) + sizeof(int) + 1); }
+static size_t md_list_lds(size_t nmax) { return nmax * kNeighbourMax * sizeof(unsigned short); }
+static size_t md_noise_lds(const Context& c, size_t nmax) {
+    return (size_t)c.md.M * 3 * nmax * (c.storage == LB_STORE_F64 ? sizeof(double) : sizeof(float));
+}
+
 // Verlet lists go to LDS when positions (two buffers), node/bond arrays and lists fit
 static bool md_lists_in_lds(const Context& c) {
     const size_t nmax = (size_t)md_nmax(c);
-    return nmax * (6 * sizeof(double) + sizeof(int) + 1 + kNeighbourMax * sizeof(unsigned short)) <= 150 * 1024;
+    return md_base_lds(nmax) + md_list_lds(nmax) <= kMDLdsBudget;
 }
 
-size_t md_lds_bytes(const Context& c) {
+// the per-step table of random forces, when several lanes share a bead and it fits
+static bool md_noise_in_lds(const Context& c, int G) {
     const size_t nmax = (size_t)md_nmax(c);
-    size_t b = nmax * (6 * sizeof(double) + sizeof(int) + 1);
-    if (md_lists_in_lds(c)) b += nmax * kNeighbourMax * sizeof(unsigned short);
+    size_t b = md_base_lds(nmax) + md_noise_lds(c, nmax);
+    if (md_lists_in_lds(c)) b += md_list_lds(nmax);
+    return G > 1 && b <= kMDLdsBudget;
+}
+
+static size_t md_lds_bytes(const Context& c, int G) {
+    const size_t nmax = (size_t)md_nmax(c);
+    size_t b = md_base_lds(nmax);
+    if (md_lists_in_lds(c)) b += md_list_lds(nmax);
+    if (md_noise_in_lds(c, G)) b += md_noise_lds(c, nmax);
     return b;
+}
+
+int md_default_lanes(int max_beads) {
+    // lanes per bead: up to ~512 threads, so that each SIMD has two waves to interleave
+    // (measured faster than one wave per SIMD for 100 beads, although the per-bead work
+    // is repeated by every lane of a group); beyond 256 beads one lane per bead
+    const int m = std::max(max_beads, 1);
+    if (m <= 32) return 16;
+    if (m <= 64) return 8;
+    if (m <= 128) return 4;
+    if (m <= 256) return 2;
+    return 1;
+}
+
+bool md_lanes_valid(int lanes, int max_beads) {
+    if (lanes == 1) return max_beads <= 4096;
+    return (lanes == 2 || lanes == 4 || lanes == 8 || lanes == 16) && (long long)lanes * max_beads <= 512;
 }
 
 template <class Real, int G, int BPT, bool PER, int MAXT>
@@ -790,7 +919,8 @@ static hipError_t launch_md_t(const Context& c, const void* cur, int mode, int b
     a.mode = mode;
     a.nmax = md_nmax(c);
     a.list_in_lds = md_lists_in_lds(c) ? 1 : 0;
-    const size_t lds = md_lds_bytes(c);
+    a.noise_in_lds = md_noise_in_lds(c, G) ? 1 : 0;
+    const size_t lds = md_lds_bytes(c, G);
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)k_md<Real, G, BPT, PER, MAXT>,
@@ -805,16 +935,19 @@ static hipError_t launch_md_t(const Context& c, const void* cur, int mode, int b
 
 template <class Real, bool PER>
 static hipError_t launch_md_g(const Context& c, const void* cur, int mode, hipStream_t s) {
-    // lanes per bead: up to ~512 threads, so that each SIMD has two waves to interleave
-    // (measured faster than one wave per SIMD for 100 beads, although the per-bead work
-    // is repeated by every lane of a group); beyond 256 beads one lane per bead, beyond
-    // 512 the 1024-thread bound, beyond 1024 up to 4 beads per lane
+    // G lanes per bead (the context's choice); with one lane per bead the 512-thread
+    // bound up to 512 beads, the 1024-thread bound beyond, up to 4 beads per lane
     const int m = std::max(c.max_beads, 1);
+    const int G = c.md_lanes > 0 ? c.md_lanes : md_default_lanes(m);
+    if (!md_lanes_valid(G, m)) return hipErrorInvalidValue;
     auto blk = [](int t) { return std::min(1024, (t + 63) / 64 * 64); };
-    if (m <= 32) return launch_md_t<Real, 16, 1, PER, 512>(c, cur, mode, blk(16 * m), s);
-    if (m <= 64) return launch_md_t<Real, 8, 1, PER, 512>(c, cur, mode, blk(8 * m), s);
-    if (m <= 128) return launch_md_t<Real, 4, 1, PER, 512>(c, cur, mode, blk(4 * m), s);
-    if (m <= 256) return launch_md_t<Real, 2, 1, PER, 512>(c, cur, mode, blk(2 * m), s);
+    switch (G) {
+        case 16: return launch_md_t<Real, 16, 1, PER, 512>(c, cur, mode, blk(16 * m), s);
+        case 8: return launch_md_t<Real, 8, 1, PER, 512>(c, cur, mode, blk(8 * m), s);
+        case 4: return launch_md_t<Real, 4, 1, PER, 512>(c, cur, mode, blk(4 * m), s);
+        case 2: return launch_md_t<Real, 2, 1, PER, 512>(c, cur, mode, blk(2 * m), s);
+        default: break;
+    }
     if (m <= 512) return launch_md_t<Real, 1, 1, PER, 512>(c, cur, mode, blk(m), s);
     if (m <= 1024) return launch_md_t<Real, 1, 1, PER, 1024>(c, cur, mode, blk(m), s);
     if (m <= 2048) return launch_md_t<Real, 1, 2, PER, 1024>(c, cur, mode, 1024, s);

@@ -32,8 +32,8 @@ LB_ERR_BEAD_IN_SOLID, LB_ERR_BEAD_OUTSIDE, LB_ERR_NONFINITE, LB_ERR_BOND_STRETCH
     1, 2, 4, 8, 16)
 
 EXPORTED = ["lb_required_bytes", "lb_validate_config", "lb_init", "lb_step", "lb_couple", "md_step",
-            "lb_moments", "lb_moments_bytes", "lb_block_size", "lb_launch_shape", "lb_destroy", "lb_strerror",
-            "lb_last_error_message"]
+            "lb_moments", "lb_moments_bytes", "lb_block_size", "lb_launch_shape", "lb_md_lanes", "lb_destroy",
+            "lb_strerror", "lb_last_error_message"]
 
 
 class lbmd_wall(C.Structure):
@@ -65,7 +65,7 @@ class lbmd_config(C.Structure):
     _fields_ = [("n_replicas", C.c_int), ("replicas", C.POINTER(lbmd_replica)), ("storage", C.c_int),
                 ("md", lbmd_md_params), ("init", C.POINTER(lbmd_initial_state)),
                 ("block_size", C.c_int), ("lattice_mapping", C.c_int), ("xcd_order", C.c_int),
-                ("flags", C.c_uint)]
+                ("md_lanes", C.c_int), ("flags", C.c_uint)]
 
 
 class lbmd_buffers(C.Structure):
@@ -96,6 +96,7 @@ def lib():
         L.lb_moments_bytes.restype = C.c_size_t
         L.lb_block_size.argtypes = [C.c_void_p]
         L.lb_launch_shape.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.lb_md_lanes.argtypes = [C.c_void_p]
         L.lb_destroy.argtypes = [C.c_void_p]
         L.lb_strerror.argtypes = [C.c_int]
         L.lb_strerror.restype = C.c_char_p
@@ -129,7 +130,7 @@ class Config:
 
     def __init__(self, replicas, md, storage: int, init: Optional[dict] = None,
                  block_size: int = 0, flags: int = 0, mapping: int = LB_MAP_AUTO,
-                 xcd_order: int = LB_XCD_AUTO):
+                 xcd_order: int = LB_XCD_AUTO, md_lanes: int = 0):
         self._keep: List[object] = []
         n = len(replicas)
         self.reps = (lbmd_replica * n)()
@@ -169,6 +170,7 @@ class Config:
         self.cfg.block_size = int(block_size)
         self.cfg.lattice_mapping = int(mapping)
         self.cfg.xcd_order = int(xcd_order)
+        self.cfg.md_lanes = int(md_lanes)
         self.cfg.flags = int(flags)
 
     def validate(self) -> int:
@@ -183,14 +185,14 @@ class Simulation:
 
     def __init__(self, replicas, md, storage: int, init: Optional[dict] = None,
                  block_size: int = 0, flags: int = 0, device_buffers: bool = True,
-                 mapping: int = LB_MAP_AUTO, xcd_order: int = LB_XCD_AUTO):
+                 mapping: int = LB_MAP_AUTO, xcd_order: int = LB_XCD_AUTO, md_lanes: int = 0):
         import torch
 
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the lbmd library runs on an MI355X (gfx950) only")
         self.replicas = list(replicas)
         self.storage = storage
-        self._cfg = Config(self.replicas, md, storage, init, block_size, flags, mapping, xcd_order)
+        self._cfg = Config(self.replicas, md, storage, init, block_size, flags, mapping, xcd_order, md_lanes)
         L = lib()
         self._bufs = None
         self._tensors = []
@@ -232,7 +234,15 @@ class Simulation:
         b, m, x = C.c_int(), C.c_int(), C.c_int()
         _check(lib().lb_launch_shape(self.ctx, C.byref(b), C.byref(m), C.byref(x)), "lb_launch_shape")
         return {"block": b.value, "mapping": {LB_MAP_FLAT: "flat", LB_MAP_ROWS: "rows"}[m.value],
-                "xcd_order": x.value}
+                "xcd_order": x.value, "md_lanes": self.md_lanes}
+
+    @property
+    def md_lanes(self) -> int:
+        """Lanes per bead of the bead kernel (0 without beads)."""
+        v = lib().lb_md_lanes(self.ctx)
+        if v < 0:
+            _check(v, "lb_md_lanes")
+        return v
 
     # -- observables ----------------------------------------------------------------------
     def _moments(self, replica: int, what: int, allow_unstable: bool = False) -> np.ndarray:

@@ -98,3 +98,15 @@ def test_no_gpu_needed_for_host_calls():
     c = _cfg([_rep()])
     assert c.validate() == B.LB_OK
     assert c.required_bytes(B.LB_BUF_POPS) == ((19 * 32 * 16 * 16 * 4 + 255) // 256) * 256
+
+
+def test_md_lanes_validation():
+    # lanes x beads of the largest replica <= 512 for grouped lanes; one lane up to 4096 beads
+    one = [_rep()]  # 10 beads
+    for lanes, ok in ((0, True), (1, True), (2, True), (4, True), (8, True), (16, True), (3, False),
+                      (32, False), (-1, False)):
+        assert (_cfg(one, md_lanes=lanes).validate() == B.LB_OK) == ok, lanes
+    big = [Replica(_rep().box, [100], 1)]
+    assert _cfg(big, md_lanes=4).validate() == B.LB_OK
+    assert _cfg(big, md_lanes=8).validate() == B.LB_EINVAL
+    assert _cfg(big, md_lanes=1).validate() == B.LB_OK

@@ -268,6 +268,33 @@ def test_graph_and_direct_launches_bitwise_equal():
         assert np.array_equal(f, out[0][0]) and np.array_equal(r, out[0][1])
 
 
+def test_autotune_restores_state():
+    """LB_CFG_AUTOTUNE times lattice launches and bead-kernel steps at lb_init; afterwards
+    the state is the initial one, and the run equals one with the chosen lanes per bead
+    given explicitly."""
+    from paper_0710_1272_amd import lbmd as B
+    w = WC.c2_translocation(F32)
+    rep = w.replicas[0]
+    beads = G.replica_beads(rep, w.md)
+    with gpu_sim([rep], w.md, F32, beads=beads, flags=B.LB_CFG_AUTOTUNE) as sim:
+        shape = sim.launch_shape()
+        log(f"autotuned shape {shape}")
+        r0, v0 = sim.beads()
+        assert np.array_equal(r0, beads) and not np.any(v0)
+        assert sim.status() == (0, 0)
+        tr = sim.transloc()
+        assert tr["t_done"] == -1 and tr["step"] == 0
+        ora_f = O.equilibrium_populations(rep.box, np.full(rep.box.nodes, 1.0), np.zeros((3, rep.box.nodes)))
+        assert max_rel(sim.populations(), ora_f, _fluid(rep.box)) < 1e-7
+        sim.step(10)
+        f_a, r_a = sim.populations(), sim.beads()[0]
+    with gpu_sim([rep], w.md, F32, beads=beads, md_lanes=shape["md_lanes"]) as sim:
+        sim.step(10)
+        f_b, r_b = sim.populations(), sim.beads()[0]
+    assert max_rel(f_a, f_b, _fluid(rep.box)) < 1e-6
+    assert np.max(np.abs(r_a - r_b)) < 1e-6
+
+
 def test_nan_density_sets_error_word():
     from paper_0710_1272_amd import lbmd as B
     box = Box(16, 8, 8, (PERIODIC,) * 3)
@@ -292,9 +319,11 @@ def _dense_chain(box, n, seed, sigma_gen=1.75):
 
 @pytest.mark.parametrize("storage,tol", [(F64, 1e-11), (F32, 2e-4)], ids=["f64", "f32"])
 @pytest.mark.parametrize("periodic", [False, True], ids=["pore", "periodic"])
-def test_md_step_dense_contacts(storage, tol, periodic):
+@pytest.mark.parametrize("lanes", [0, 1, 2, 4, 8], ids=lambda g: f"lanes{g}")
+def test_md_step_dense_contacts(storage, tol, periodic, lanes):
     """One INTERP + md_step (20 substeps) with WCA contacts, wall, pore and faces (or
-    periodic images) against the oracle's interpolation and substeps."""
+    periodic images) against the oracle's interpolation and substeps, for every choice
+    of lanes per bead (0: the default for the bead count)."""
     if periodic:
         box = Box(20, 16, 16, (PERIODIC,) * 3, (), 1.0)
         chains = [40, 8]
@@ -307,6 +336,8 @@ def test_md_step_dense_contacts(storage, tol, periodic):
     if periodic:
         a = a + np.array([12.0, 0.0, 0.0])  # let the chain cross the periodic x boundary
     beads = np.concatenate([a, b])
+    if lanes * len(beads) > 512:
+        pytest.skip(f"{lanes} lanes per bead need at most {512 // lanes} beads")
     rep = Replica(box, chains, 31)
     rho, u = G.random_small_flow(box, 5, du=0.01)
     from paper_0710_1272_amd import lbmd as B
@@ -316,7 +347,8 @@ def test_md_step_dense_contacts(storage, tol, periodic):
     assert np.max(np.abs(F0)) > 0.5, "the configuration must have active contacts"
     r_o, v_o = ora.r.copy(), ora.v.copy()
     fbar_o, flags_o = O.md_substeps(box, md, chains, r_o, v_o, u_o, 7, rep.seed)
-    with gpu_sim([rep], md, storage, rho, u, beads=beads, step0=7) as sim:
+    with gpu_sim([rep], md, storage, rho, u, beads=beads, step0=7, md_lanes=lanes) as sim:
+        log(f"  lanes per bead {sim.md_lanes}")
         sim.couple(B.LB_COUPLE_INTERP)
         sim.md_step()
         r_g, v_g = sim.beads()
@@ -332,6 +364,35 @@ def test_md_step_dense_contacts(storage, tol, periodic):
     assert np.max(np.abs(r_g - r_o)) < tol
     assert np.max(np.abs(v_g - v_o)) < tol * scale_v
     assert np.max(np.abs(fb_g - fbar_o)) < tol * scale_v
+
+
+@pytest.mark.parametrize("storage,tol", [(F64, 1e-11), (F32, 2e-4)], ids=["f64", "f32"])
+def test_md_step_wall_image_across_periodic_x(storage, tol):
+    """A wall next to the periodic x boundary: beads whose unwrapped x lies beyond the box
+    feel the wall through their periodic image (positions are never wrapped)."""
+    box = Box(24, 16, 16, (PERIODIC,) * 3, ((2, 4, 7, 9, 7, 9),), 1.0)
+    md = MDParams()
+    # a chain along y at unwrapped x = 24.55 (image 0.55, 0.95 from the wall face at 1.5)
+    beads = np.array([[24.55, 1.0 + 1.2 * k, 3.0] for k in range(6)])
+    rep = Replica(box, [6], 17)
+    rho, u = G.random_small_flow(box, 4, du=0.01)
+    from paper_0710_1272_amd import lbmd as B
+    ora = oracle_sim(rep, md, rho, u, beads=beads, step0=3)
+    u_o, node_o = O.interp(box, ora.f, ora.r)
+    r_o, v_o = ora.r.copy(), ora.v.copy()
+    fbar_o, flags_o = O.md_substeps(box, md, [6], r_o, v_o, u_o, 3, rep.seed)
+    assert O.wall_distance(box, beads[0])[0] < 1.0, "the image must be within the wall cutoff"
+    with gpu_sim([rep], md, storage, rho, u, beads=beads, step0=3) as sim:
+        sim.couple(B.LB_COUPLE_INTERP)
+        sim.md_step()
+        r_g, v_g = sim.beads()
+        word, _ = sim.status()
+    log(f"  wall image: |dr| {np.max(np.abs(r_g - r_o)):.2e} |dv| {np.max(np.abs(v_g - v_o)):.2e} "
+        f"max|v| {np.max(np.abs(v_o)):.2e}")
+    assert word == flags_o == 0
+    assert np.max(np.abs(v_o[:, 0])) > 0.1, "the wall force must act"
+    assert np.max(np.abs(r_g - r_o)) < tol
+    assert np.max(np.abs(v_g - v_o)) < tol * max(1.0, np.max(np.abs(v_o)))
 
 
 @pytest.mark.parametrize("storage,tol", [(F64, 1e-12), (F32, 1e-5)], ids=["f64", "f32"])
