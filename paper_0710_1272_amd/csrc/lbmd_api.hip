@@ -112,7 +112,7 @@ BeadLayout bead_layout(int ntot, int n_reps, size_t rs) {
     L.fbar = off;     off += align256(3 * N * rs);
     L.node = off;     off += align256(N * sizeof(int));
     L.bond_next = off; off += align256(N);
-    L.agg_node = off; off += align256(N * sizeof(int));
+    L.agg_at = off;   off += align256(2 * N * sizeof(long long));
     L.agg_f = off;    off += align256(3 * N * rs);
     L.rep_of = off;   off += align256(N * sizeof(int));
     L.diag = off;     off += align256(8 * (size_t)std::max(n_reps, 1) * sizeof(double));
@@ -246,7 +246,7 @@ int setup_beads(Context& c, const lbmd_config* cfg) {
     p->fbar = (Real*)(base + L.fbar);
     p->node = (int*)(base + L.node);
     p->bond_next = (unsigned char*)(base + L.bond_next);
-    p->agg_node = (int*)(base + L.agg_node);
+    p->agg_at = (long long*)(base + L.agg_at);
     p->agg_f = (Real*)(base + L.agg_f);
     p->rep_of = (int*)(base + L.rep_of);
     p->diag = (double*)(base + L.diag);
@@ -288,7 +288,8 @@ int setup_beads(Context& c, const lbmd_config* cfg) {
         HIP_TRY(hipMemset(p->fbar, 0, 3 * (size_t)N * sizeof(Real)));
         HIP_TRY(hipMemset(p->agg_f, 0, 3 * (size_t)N * sizeof(Real)));
         HIP_TRY(hipMemcpy(p->node, minus1.data(), N * sizeof(int), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(p->agg_node, minus1.data(), N * sizeof(int), hipMemcpyHostToDevice));
+        std::vector<long long> none(2 * (size_t)N, -1);
+        HIP_TRY(hipMemcpy(p->agg_at, none.data(), 2 * (size_t)N * sizeof(long long), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(p->bond_next, bn.data(), N, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(p->rep_of, rep_of.data(), N * sizeof(int), hipMemcpyHostToDevice));
     }

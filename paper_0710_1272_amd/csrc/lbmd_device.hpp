@@ -333,8 +333,9 @@ struct BeadPtrs {
     Real* fbar;         // [3][Ntot] substep-averaged drag + random force
     int* node;          // [Ntot] nearest node (within the replica), -1 on solid
     unsigned char* bond_next;  // [Ntot] 1 if bead i and i+1 are bonded
-    int* agg_node;      // [Ntot] node of a bead that leads its node's sum, else -1
-    Real* agg_f;        // [3][Ntot] summed Fbar of the beads sharing agg_node
+    long long* agg_at;  // [2][Ntot]: element offset of population 0 at the node a bead leads
+                        // (pop_base + node, else -1), and the replica's V (population stride)
+    Real* agg_f;        // [3][Ntot] summed Fbar of the beads sharing the node a bead leads
     int* rep_of;        // [Ntot] replica of each bead
     double* diag;       // [n_replicas][8]: N_T, t_done, com x,y,z, last step, list builds, -
     unsigned short* nlist;  // [kNeighbourMax][Ntot] Verlet neighbours (index within the replica)

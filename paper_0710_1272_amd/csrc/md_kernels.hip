@@ -177,6 +177,14 @@ __device__ __forceinline__ Real fast_rcp(Real x) {
     else return Real(1) / x;
 }
 
+// 1/sqrt(x): the hardware reciprocal square root in FP32 (about 1 ulp), sqrt and an
+// exact division in FP64
+template <class Real>
+__device__ __forceinline__ Real fast_rsqrt(Real x) {
+    if constexpr (sizeof(Real) == 4) return __builtin_amdgcn_rsqf(x);
+    else return Real(1) / sqrt(x);
+}
+
 // -(1/r) dV/dr of WCA at squared distance r2 (0 beyond the cutoff)
 template <class Real>
 __device__ __forceinline__ Real wca_coef(Real r2, Real eps, Real sig2, Real rc2) {
@@ -498,8 +506,10 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
     if (noise_lds) {
         // the G lanes of a bead share its M Philox draws instead of each lane drawing all
         // of them; the table is read from the next barrier on
-        const int i = grp;
-        if (own[0]) {
+#pragma unroll
+        for (int k = 0; k < BPT; ++k) {
+            const int i = grp + k * NG;
+            if (!own[k]) continue;
             for (int s = gl; s < M; s += G) {
                 const U4 rnd = philox4x32_10(U4{(uint32_t)i, (uint32_t)step, (uint32_t)s, 1u}, seed_lo, seed_hi);
                 NZ[(3 * s + 0) * nmax + i] = A * centred_uniform<Real>(rnd.x);
@@ -563,8 +573,11 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
     load_slots();
     // rebuild vote: one flag per wave, double-buffered so that one barrier per substep
     // separates the writes of a substep from its reads and from the next substep's writes
-    __shared__ int vote[2][16];
+    __shared__ __align__(16) unsigned char vote[2][16];
     const int wave = tid >> 6, n_waves = (blockDim.x + 63) >> 6;
+    // flags of absent waves stay 0 (they are read whole, as 16 bytes, after each barrier;
+    // no wave writes them, so clearing them here races with nothing)
+    if (tid < 32 && (tid & 15) >= n_waves) vote[tid >> 4][tid & 15] = 0;
     const bool x_periodic = PERIODIC && !GM.fs[0];
 
     for (int sub = 0; sub < M; ++sub) {
@@ -617,11 +630,17 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
             };
 #pragma unroll
             for (int s = 0; s < K; ++s) {
-                if (s < nslot[k]) {
-                    Real d[3];
-                    const Real r2 = separation_v<Real, PERIODIC>(r[k], pj[s], per, nd, d);
-                    wca(d, r2);
-                }
+                // without branches: an unused slot or a pair beyond the cutoff adds 0
+                Real d[3];
+                const Real r2 = separation_v<Real, PERIODIC>(r[k], pj[s], per, nd, d);
+                const bool hit = s < nslot[k] && r2 < rc2;
+                const Real ir2 = fast_rcp<Real>(hit ? r2 : Real(1));
+                const Real s2 = sig2 * ir2;
+                const Real s6 = s2 * s2 * s2;
+                const Real c = hit ? eps24 * (Real(2) * s6 * s6 - s6) * ir2 : Real(0);
+                fx += c * d[0];
+                fy += c * d[1];
+                fz += c * d[2];
             }
             const bool overflow = cnt[k] > kNeighbourMax;
             const int lim = overflow ? n : cnt[k];
@@ -641,16 +660,16 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
             F[k][0] = group_sum<G>(fx);
             F[k][1] = group_sum<G>(fy);
             F[k][2] = group_sum<G>(fz);
-            // harmonic bonds to the chain neighbours
+            // harmonic bonds to the chain neighbours, -k (len - r0)/len d = -k (1 - r0/len) d
+            // (d points from j to i: the bond pulls i towards j when stretched); an
+            // absent neighbour is the bead itself and adds 0
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
                 const bool on = side == 0 ? bpk[k] : bnk[k];
-                if (!on) continue;
                 Real d[3];
-                const Real len = sqrt(separation_v<Real, PERIODIC>(r[k], side == 0 ? pm : pp, per, nd, d));
-                if (len > Real(2) * r0) flags |= LB_ERR_BOND_STRETCH;
-                // d points from j to i: the bond pulls i towards j when stretched
-                const Real coef = -kb * (len - r0) * fast_rcp<Real>(len);
+                const Real b2 = separation_v<Real, PERIODIC>(r[k], side == 0 ? pm : pp, per, nd, d);
+                if (on && b2 > Real(4) * r0 * r0) flags |= LB_ERR_BOND_STRETCH;
+                const Real coef = on ? -kb * (Real(1) - r0 * fast_rsqrt<Real>(b2)) : Real(0);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) F[k][c] += coef * d[c];
             }
@@ -731,8 +750,8 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
         const bool wave_moved = __ballot(moved) != 0ull;
         if ((tid & 63) == 0) vote[vb][wave] = wave_moved ? 1 : 0;
         __syncthreads();
-        int any_moved = 0;
-        for (int w = 0; w < n_waves; ++w) any_moved |= vote[vb][w];
+        const uint4 vv = *(const uint4*)vote[vb];
+        const bool any_moved = (vv.x | vv.y | vv.z | vv.w) != 0u;
         cur ^= 1;
         if (any_moved && sub + 1 < M) {
             ++builds;
@@ -801,7 +820,8 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
         }
         if (gl == 0) {
             const int gi = b0 + i;
-            a.b.agg_node[gi] = lead ? me : -1;
+            a.b.agg_at[gi] = lead ? R.pop_base + me : -1;
+            a.b.agg_at[NT + gi] = R.V;
 #pragma unroll
             for (int c = 0; c < 3; ++c) a.b.agg_f[c * NT + gi] = lead ? s[c] : Real(0);
         }
@@ -829,29 +849,41 @@ __global__ __launch_bounds__(256) void k_spread(const Replica* __restrict__ reps
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (bump_step && i == 0) st->step += 1;
     if (i >= b.ntot) return;
-    const int node = b.agg_node[i];
-    if (node < 0) return;
-    const Replica& R = reps[b.rep_of[i]];
+    // one round trip for everything a leader needs: where, stride, force
+    const long long at = b.agg_at[i];
+    const long long V = b.agg_at[b.ntot + i];
     const Rl F[3] = {(Rl)b.agg_f[i], (Rl)b.agg_f[b.ntot + i], (Rl)b.agg_f[2 * b.ntot + i]};
-    typename C::T* __restrict__ base = dst + R.pop_base + node;
-    const long long V = R.V;
-    // all 18 moving populations are read before any is written
-    Rl f[Q];
-    md_for_pops([&](auto P) {
+    if (at < 0) return;
+    typename C::T* __restrict__ base = dst + at;
+    // S_p = -(w_p / c_s^2) Fbar . c_p with c_s^2 = 1/3
+    auto source = [&](auto P) {
         constexpr int p = decltype(P)::value;
-        if constexpr (p != 0) f[p] = C::template load<p>(base[(long long)p * V]);
-    });
-    md_for_pops([&](auto P) {
-        constexpr int p = decltype(P)::value;
-        if constexpr (p != 0) {
-            Rl fc = 0;
-            if constexpr (cx_of(p) != 0) fc += Rl(cx_of(p)) * F[0];
-            if constexpr (cy_of(p) != 0) fc += Rl(cy_of(p)) * F[1];
-            if constexpr (cz_of(p) != 0) fc += Rl(cz_of(p)) * F[2];
-            // S_p = -(w_p / c_s^2) Fbar . c_p with c_s^2 = 1/3
-            base[(long long)p * V] = C::template store<p>(f[p] - Rl(3) * w_of<Rl>(p) * fc);
-        }
-    });
+        Rl fc = 0;
+        if constexpr (cx_of(p) != 0) fc += Rl(cx_of(p)) * F[0];
+        if constexpr (cy_of(p) != 0) fc += Rl(cy_of(p)) * F[1];
+        if constexpr (cz_of(p) != 0) fc += Rl(cz_of(p)) * F[2];
+        return -Rl(3) * w_of<Rl>(p) * fc;
+    };
+    if constexpr (S == LB_STORE_F32 || S == LB_STORE_F64) {
+        // full-precision storage: hardware float atomics without return (each node has one
+        // leader, so no two threads add to one element and the result is deterministic)
+        md_for_pops([&](auto P) {
+            constexpr int p = decltype(P)::value;
+            if constexpr (p != 0) (void)unsafeAtomicAdd(&base[(long long)p * V], source(P));
+        });
+    } else {
+        // 16-bit storage: decode, add, re-encode; all 18 moving populations are read
+        // before any is written
+        Rl f[Q];
+        md_for_pops([&](auto P) {
+            constexpr int p = decltype(P)::value;
+            if constexpr (p != 0) f[p] = C::template load<p>(base[(long long)p * V]);
+        });
+        md_for_pops([&](auto P) {
+            constexpr int p = decltype(P)::value;
+            if constexpr (p != 0) base[(long long)p * V] = C::template store<p>(f[p] + source(P));
+        });
+    }
 }
 
 __global__ void k_bump(RunState* st) { st->step += 1; }
