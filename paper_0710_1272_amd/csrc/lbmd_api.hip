@@ -598,10 +598,11 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
     md.sigma_w2 = m.sigma_w * m.sigma_w;
     md.rcw2 = std::pow(2.0, 1.0 / 3.0) * md.sigma_w2;
     md.rcw = std::sqrt(md.rcw2);
-    // Verlet skin: the list holds pairs closer than rc + skin and is rebuilt as soon as
-    // any bead has moved skin/2 since the last build, so no interacting pair is missed
+    // Verlet skin: the list holds pairs closer than rc + skin (plus 1e-3 for the rounding
+    // of the FP32 displacement test) and is rebuilt as soon as any bead has moved skin/2
+    // since the last build, so no interacting pair is missed
     const double skin = 0.6;
-    md.rl2 = (std::sqrt(md.rc2) + skin) * (std::sqrt(md.rc2) + skin);
+    md.rl2 = (std::sqrt(md.rc2) + skin + 1e-3) * (std::sqrt(md.rc2) + skin + 1e-3);
     md.half_skin2 = 0.25 * skin * skin;
     md.f_drive = m.drive_sign * m.f_drive;
 

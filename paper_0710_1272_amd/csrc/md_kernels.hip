@@ -97,77 +97,61 @@ __device__ __forceinline__ Geom load_geom(const Replica& R) {
     return g;
 }
 
-__device__ __forceinline__ bool geom_is_pore(const Geom& G, const int* c) {
-    bool s = false;
-#pragma unroll
-    for (int k = 0; k < LB_MAX_WALLS; ++k) {
-        if (k >= G.n_walls) break;
-        const int* w = G.wall[k];
-        s = s || (c[0] >= w[0] && c[0] <= w[1] && pore_open(w) && c[1] >= w[2] && c[1] <= w[3] &&
-                  c[2] >= w[4] && c[2] <= w[5]);
-    }
-    return s;
-}
-
-// nearest node floor(r + 1/2): free-slip axes clamp (NaN -> 0), periodic axes wrap
+// Whether the nearest node floor(r + 1/2) of r is a node of wall w's pore.  On a
+// free-slip axis floor(t) in [lo, hi] is decided as lo <= t < hi + 1 on the same rounded
+// t = r + 1/2, with the index clamping into the box kept (a bound on the box face always
+// holds); a periodic axis wraps the index as the node lookup does.
 template <bool PERIODIC>
-__device__ __forceinline__ void geom_ngp(const Geom& G, const double* r, int* c) {
+__device__ __forceinline__ bool wall_pore_node(const Geom& G, const int* w, const double* r) {
+    if (!pore_open(w)) return false;
+    bool in = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        double t = floor(r[a] + 0.5);
-        if (!(t >= -1e9 && t <= 1e9)) t = 0.0;  // non-finite or absurd
-        int k = (int)t;
+        const int lo = w[2 * a], hi = w[2 * a + 1];
+        const double t = r[a] + 0.5;
         if (PERIODIC && !G.fs[a]) {
-            k %= G.n[a];
+            double f = floor(t);
+            if (!(f >= -1e9 && f <= 1e9)) f = 0.0;  // non-finite or absurd
+            int k = (int)f % G.n[a];
             if (k < 0) k += G.n[a];
+            in = in && k >= lo && k <= hi;
         } else {
-            k = k < 0 ? 0 : (k > G.n[a] - 1 ? G.n[a] - 1 : k);
+            in = in && (lo <= 0 || t >= (double)lo) && (hi >= G.n[a] - 1 || t < (double)(hi + 1));
         }
-        c[a] = k;
     }
+    return in;
 }
 
-// Squared distance from r to the nearest solid surface, and the vector from that
-// surface point to r.  Solid node cubes span [i - 1/2, i + 1/2], so a wall is its slab
-// X0..X1 minus the pore prism Y0..Y1 x Z0..Z1.  Outside the prism (in y, z) the nearest
-// solid point lies straight along x, on the slab; inside it, on the nearest of the four
-// prism sides, at x clamped into the slab.  Ties go to the earlier wall and to the sides
-// in the order y-low, y-high, z-low, z-high.
+// Squared distance from r to the nearest solid surface of wall w, and the vector from
+// that surface point to r (xw: x wrapped into the box on a periodic axis).  Solid node
+// cubes span [i - 1/2, i + 1/2], so a wall is its slab X0..X1 minus the pore prism
+// Y0..Y1 x Z0..Z1.  Outside the prism (in y, z) the nearest solid point lies straight
+// along x, on the slab; inside it, on the nearest of the four prism sides, at x clamped
+// into the slab.  Ties go to the sides in the order y-low, y-high, z-low, z-high.
 template <bool PERIODIC>
-__device__ inline double geom_wall_dist2(const Geom& G, const double* rin, double* dv) {
-    double r[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-        r[a] = (PERIODIC && !G.fs[a]) ? rin[a] - G.n[a] * floor((rin[a] + 0.5) / G.n[a]) : rin[a];
-    double best2 = HUGE_VAL;
-    dv[0] = dv[1] = dv[2] = 0.0;
-#pragma unroll
-    for (int k = 0; k < LB_MAX_WALLS; ++k) {
-        if (k >= G.n_walls) break;
-        const int* w = G.wall[k];
-        const double X0 = w[0] - 0.5, X1 = w[1] + 0.5;
-        const double Y0 = w[2] - 0.5, Y1 = w[3] + 0.5, Z0 = w[4] - 0.5, Z1 = w[5] + 0.5;
-        const double dx = r[0] - fmin(fmax(r[0], X0), X1);
-        double dy = 0.0, dz = 0.0;
-        if (pore_open(w) && r[1] >= Y0 && r[1] <= Y1 && r[2] >= Z0 && r[2] <= Z1) {
-            double side = r[1] - Y0;
-            dy = side;
-            double t = Y1 - r[1];
-            if (t < side) { side = t; dy = -t; }
-            t = r[2] - Z0;
-            if (t < side) { side = t; dy = 0.0; dz = t; }
-            t = Z1 - r[2];
-            if (t < side) { side = t; dy = 0.0; dz = -t; }
-        }
-        const double q = dx * dx + dy * dy + dz * dz;
-        if (q < best2) {
-            best2 = q;
-            dv[0] = dx;
-            dv[1] = dy;
-            dv[2] = dz;
-        }
+__device__ __forceinline__ double wall_dist2(const Geom& G, const int* w, const double* rin, double xw,
+                                             double* dv) {
+    double ry = rin[1], rz = rin[2];
+    if (PERIODIC && !G.fs[1]) ry -= G.n[1] * floor((ry + 0.5) / G.n[1]);
+    if (PERIODIC && !G.fs[2]) rz -= G.n[2] * floor((rz + 0.5) / G.n[2]);
+    const double X0 = w[0] - 0.5, X1 = w[1] + 0.5;
+    const double Y0 = w[2] - 0.5, Y1 = w[3] + 0.5, Z0 = w[4] - 0.5, Z1 = w[5] + 0.5;
+    const double dx = xw - fmin(fmax(xw, X0), X1);
+    double dy = 0.0, dz = 0.0;
+    if (pore_open(w) && ry >= Y0 && ry <= Y1 && rz >= Z0 && rz <= Z1) {
+        double side = ry - Y0;
+        dy = side;
+        double t = Y1 - ry;
+        if (t < side) { side = t; dy = -t; }
+        t = rz - Z0;
+        if (t < side) { side = t; dy = 0.0; dz = t; }
+        t = Z1 - rz;
+        if (t < side) { side = t; dy = 0.0; dz = -t; }
     }
-    return best2;
+    dv[0] = dx;
+    dv[1] = dy;
+    dv[2] = dz;
+    return dx * dx + dy * dy + dz * dz;
 }
 
 // 1/x: the hardware reciprocal in FP32 (about 1 ulp), an exact division in FP64
@@ -554,10 +538,29 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
     }
     constexpr int K = SlotsPerLane<G, BPT, MAXT>::K;
     int slot[BPT][K], nslot[BPT];
+    // Beads within reach of a wall slab or a free-slip face.  Decided at each list build
+    // with the margin skin/2: until the next build no bead moves farther than that, so a
+    // bead outside these zones needs none of the wall, pore or face terms (all zero) and
+    // cannot have left the box.
+    const bool x_periodic = PERIODIC && !GM.fs[0];
+    const double zone = md.rcw + sqrt(md.half_skin2) + 1e-3;
+    bool nearw[BPT], nearf[BPT];
     auto load_slots = [&]() {
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
             const int i = grp + k * NG;
+            const double xw = x_periodic ? r[k][0] - nd[0] * floor((r[k][0] + 0.5) / nd[0]) : r[k][0];
+            bool w_near = false, f_near = false;
+#pragma unroll
+            for (int w = 0; w < LB_MAX_WALLS; ++w) {
+                if (w >= GM.n_walls) break;
+                w_near = w_near || (xw > GM.wall[w][0] - 0.5 - zone && xw < GM.wall[w][1] + 0.5 + zone);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (GM.fs[c]) f_near = f_near || !(r[k][c] + 0.5 >= zone && (nn[c] - 0.5) - r[k][c] >= zone);
+            nearw[k] = w_near;
+            nearf[k] = f_near;
             nslot[k] = 0;
 #pragma unroll
             for (int s = 0; s < K; ++s) {
@@ -578,7 +581,6 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
     // flags of absent waves stay 0 (they are read whole, as 16 bytes, after each barrier;
     // no wave writes them, so clearing them here races with nothing)
     if (tid < 32 && (tid & 15) >= n_waves) vote[tid >> 4][tid & 15] = 0;
-    const bool x_periodic = PERIODIC && !GM.fs[0];
 
     for (int sub = 0; sub < M; ++sub) {
         const double* PX = P + cur * 3 * nmax;
@@ -674,31 +676,40 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
                 for (int c = 0; c < 3; ++c) F[k][c] += coef * d[c];
             }
             if (!(isfinite(r[k][0]) && isfinite(r[k][1]) && isfinite(r[k][2]))) flags |= LB_ERR_NONFINITE;
-            // nearest solid surface and the pore drive, only within reach of a wall slab
-            // (x wrapped on a periodic axis): a bead whose nearest node is a pore node lies
-            // within half a node of its wall's slab
+            // nearest solid surface over the walls (min, earlier wall on ties) and the pore
+            // drive, each wall only within reach of its slab (x wrapped on a periodic
+            // axis): a bead whose nearest node is a pore node lies within half a node of
+            // its wall's slab
+            if (nearw[k]) {
             const double xw = x_periodic ? r[k][0] - nd[0] * floor((r[k][0] + 0.5) / nd[0]) : r[k][0];
-            bool near_wall = false;
+            double best2 = HUGE_VAL, dvw[3] = {0.0, 0.0, 0.0};
+            bool pore = false;
 #pragma unroll
             for (int w = 0; w < LB_MAX_WALLS; ++w) {
                 if (w >= GM.n_walls) break;
-                near_wall = near_wall || (xw > GM.wall[w][0] - 0.5 - rcw && xw < GM.wall[w][1] + 0.5 + rcw);
-            }
-            if (near_wall) {
-                double dv[3];
-                const double d2w = geom_wall_dist2<PERIODIC>(GM, r[k], dv);
-                if (d2w == 0.0) {
-                    flags |= LB_ERR_BEAD_IN_SOLID;
-                } else {
-                    const Real c = wca_coef<Real>((Real)d2w, epsw, sigw2, rcw2);
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) F[k][q] += c * (Real)dv[q];
+                const int* W = GM.wall[w];
+                if (xw > W[0] - 0.5 - rcw && xw < W[1] + 0.5 + rcw) {
+                    double dv[3];
+                    const double q = wall_dist2<PERIODIC>(GM, W, r[k], xw, dv);
+                    if (q < best2) {
+                        best2 = q;
+                        dvw[0] = dv[0];
+                        dvw[1] = dv[1];
+                        dvw[2] = dv[2];
+                    }
+                    pore = pore || wall_pore_node<PERIODIC>(GM, W, r[k]);
                 }
-                int g[3];
-                geom_ngp<PERIODIC>(GM, r[k], g);
-                if (geom_is_pore(GM, g)) F[k][0] += fdrive;
+            }
+            if (best2 == 0.0) flags |= LB_ERR_BEAD_IN_SOLID;
+            if (best2 < (double)rcw2 && best2 > 0.0) {
+                const Real c = wca_coef<Real>((Real)best2, epsw, sigw2, rcw2);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) F[k][q] += c * (Real)dvw[q];
+            }
+            if (pore) F[k][0] += fdrive;
             }
             // free-slip faces at -1/2 and n - 1/2 (the WCA terms only within the cutoff)
+            if (nearf[k]) {
             Real dlo[3], dhi[3];
             bool near_face = false;
 #pragma unroll
@@ -716,6 +727,7 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
                     F[k][c] += wca_coef<Real>(dlo[c] * dlo[c], epsw, sigw2, rcw2) * dlo[c];
                     F[k][c] -= wca_coef<Real>(dhi[c] * dhi[c], epsw, sigw2, rcw2) * dhi[c];
                 }
+            }
             }
             // drag against the frozen fluid velocity and the random force
 #pragma unroll
