@@ -118,6 +118,7 @@ BeadLayout bead_layout(int ntot, int n_reps, size_t rs) {
     L.diag = off;     off += align256(8 * (size_t)std::max(n_reps, 1) * sizeof(double));
     L.nlist = off;    off += align256((size_t)kNeighbourMax * N * sizeof(unsigned short));
     L.ncount = off;   off += align256(N * sizeof(int));
+    L.rref = off;     off += align256(3 * N * sizeof(double));
     L.total = off;
     return L;
 }
@@ -252,6 +253,7 @@ int setup_beads(Context& c, const lbmd_config* cfg) {
     p->diag = (double*)(base + L.diag);
     p->nlist = (unsigned short*)(base + L.nlist);
     p->ncount = (int*)(base + L.ncount);
+    p->rref = (double*)(base + L.rref);
     p->ntot = c.ntot_beads;
     c.bead_ptrs = p;
 
@@ -600,8 +602,10 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
     md.rcw = std::sqrt(md.rcw2);
     // Verlet skin: the list holds pairs closer than rc + skin (plus 1e-3 for the rounding
     // of the FP32 displacement test) and is rebuilt as soon as any bead has moved skin/2
-    // since the last build, so no interacting pair is missed
-    const double skin = 0.6;
+    // since the last build, so no interacting pair is missed.  Lists are kept across LB
+    // steps; a wide skin makes rebuilds rare (pore beads drift ~0.2 per LB step) while
+    // the register slots still hold the typical 3-4 neighbours.
+    const double skin = 1.0;
     md.rl2 = (std::sqrt(md.rc2) + skin + 1e-3) * (std::sqrt(md.rc2) + skin + 1e-3);
     md.half_skin2 = 0.25 * skin * skin;
     md.f_drive = m.drive_sign * m.f_drive;

@@ -337,9 +337,12 @@ struct BeadPtrs {
                         // (pop_base + node, else -1), and the replica's V (population stride)
     Real* agg_f;        // [3][Ntot] summed Fbar of the beads sharing the node a bead leads
     int* rep_of;        // [Ntot] replica of each bead
-    double* diag;       // [n_replicas][8]: N_T, t_done, com x,y,z, last step, list builds, -
+    double* diag;       // [n_replicas][8]: N_T, t_done, com x,y,z, last step, list builds,
+                        // stored lists valid (1) or not (0)
     unsigned short* nlist;  // [kNeighbourMax][Ntot] Verlet neighbours (index within the replica)
     int* ncount;        // [Ntot] number of neighbours; > kNeighbourMax means overflow
+    double* rref;       // [3][Ntot] positions at the last list build (lists are kept across
+                        // LB steps while diag[7] of the replica is 1)
     int ntot;
 };
 

@@ -89,7 +89,7 @@ WorkLayout work_layout(int n_reps, int max_V, long long max_stage_nodes);
 
 // bead-buffer layout
 struct BeadLayout {
-    size_t r, v, u, fbar, node, bond_next, agg_at, agg_f, rep_of, diag, nlist, ncount, total;
+    size_t r, v, u, fbar, node, bond_next, agg_at, agg_f, rep_of, diag, nlist, ncount, rref, total;
 };
 BeadLayout bead_layout(int ntot, int n_reps, size_t real_size);
 

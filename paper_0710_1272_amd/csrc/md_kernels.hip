@@ -330,13 +330,19 @@ __device__ __forceinline__ int build_list(int i, int n, bool bn, bool bp, const 
         }
         return total;
     } else {
-        int mine = 0;
-        for (int j = gl; j < n; j += G) {
+        // one pass: each lane marks its hits j = gl + m G (m < n / G <= 512 / G^2 <= 128)
+        // in a 128-bit mask, then the group places them by an exclusive prefix of counts
+        unsigned long long hit0 = 0ull, hit1 = 0ull;
+        int mine = 0, m = 0;
+        for (int j = gl; j < n; j += G, ++m) {
             if (j == i || (j == i + 1 && bn) || (j == i - 1 && bp)) continue;
             Real d[3];
-            if (separation<Real, PERIODIC>(ri, PX, PY, PZ, j, per, nd, d) < rl2) ++mine;
+            if (separation<Real, PERIODIC>(ri, PX, PY, PZ, j, per, nd, d) < rl2) {
+                if (m < 64) hit0 |= 1ull << m;
+                else hit1 |= 1ull << (m - 64);
+                ++mine;
+            }
         }
-        // exclusive prefix over the group's lanes
         int incl = mine;
 #pragma unroll
         for (int off = 1; off < G; off <<= 1) {
@@ -346,11 +352,15 @@ __device__ __forceinline__ int build_list(int i, int n, bool bn, bool bp, const 
         int pos = incl - mine;
         const int total = __shfl(incl, G - 1, G);
         if (total <= kNeighbourMax) {
-            for (int j = gl; j < n; j += G) {
-                if (j == i || (j == i + 1 && bn) || (j == i - 1 && bp)) continue;
-                Real d[3];
-                if (separation<Real, PERIODIC>(ri, PX, PY, PZ, j, per, nd, d) < rl2)
-                    list[(size_t)(pos++) * stride] = (unsigned short)j;
+            while (hit0) {
+                const int b = __builtin_ctzll(hit0);
+                hit0 &= hit0 - 1;
+                list[(size_t)(pos++) * stride] = (unsigned short)(gl + b * G);
+            }
+            while (hit1) {
+                const int b = __builtin_ctzll(hit1);
+                hit1 &= hit1 - 1;
+                list[(size_t)(pos++) * stride] = (unsigned short)(gl + (64 + b) * G);
             }
         }
         return total;
@@ -360,9 +370,9 @@ __device__ __forceinline__ int build_list(int i, int n, bool bn, bool bp, const 
 // Each bead is owned by a group of G lanes that split its neighbour loop; every lane
 // of the group keeps the bead's state, so the per-bead terms are computed redundantly
 // without divergence.  BPT beads per group when there are more beads than groups
-// (then G = 1).  WCA pairs come from a Verlet list (radius rc + skin) rebuilt at the
-// start of every LB step and whenever a bead has moved skin/2 since the last build,
-// so the set of interacting pairs is exactly that of the all-pairs definition.
+// (then G = 1).  WCA pairs come from a Verlet list (radius rc + skin), kept across LB
+// steps and rebuilt whenever a bead has moved skin/2 since the last build, so the set
+// of interacting pairs is exactly that of the all-pairs definition.
 // Positions are double-buffered in LDS: one barrier per substep.
 template <class Real, int G, int BPT, bool PERIODIC, int MAXT>
 __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
@@ -473,19 +483,56 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
     const Real rl2 = (Real)md.rl2, hs2 = (Real)md.half_skin2;
     const Real fdrive = (Real)md.f_drive;
 
-    // neighbour lists (reference positions kept in registers)
+    // Verlet lists: kept from the previous launch (stored with the positions they were
+    // built at) unless a bead has moved skin/2 since, else rebuilt here
     double rref[BPT][3];
     int cnt[BPT];
-    int builds = 1;
+    int builds = 0;
+    double* dg = a.b.diag + 8 * blockIdx.x;
+    bool reuse = dg[7] != 0.0;
+    if (reuse) {
+        int moved = 0;
 #pragma unroll
-    for (int k = 0; k < BPT; ++k) {
-        const int i = grp + k * NG;
-        cnt[k] = 0;
+        for (int k = 0; k < BPT; ++k) {
+            const int gi = b0 + grp + k * NG;
+            cnt[k] = 0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) rref[k][c] = r[k][c];
-        if (!own[k]) continue;
-        cnt[k] = build_list<Real, G, PERIODIC>(i, n, BN[i] != 0, i > 0 && BN[i - 1] != 0, r[k], P, P + nmax,
-                                               P + 2 * nmax, per, nd, rl2, gl, lists + i, lstride);
+            for (int c = 0; c < 3; ++c) rref[k][c] = r[k][c];
+            if (!own[k]) continue;
+            Real disp2 = 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                rref[k][c] = a.b.rref[c * NT + gi];
+                const Real dd = (Real)(r[k][c] - rref[k][c]);
+                disp2 += dd * dd;
+            }
+            moved |= !(disp2 <= hs2);
+            cnt[k] = a.b.ncount[gi];
+        }
+        reuse = !__syncthreads_or(moved);
+    }
+    if (reuse) {
+        if (a.list_in_lds) {
+#pragma unroll
+            for (int k = 0; k < BPT; ++k) {
+                const int i = grp + k * NG;
+                if (!own[k]) continue;
+                const int m = cnt[k] < kNeighbourMax ? cnt[k] : kNeighbourMax;
+                for (int q = gl; q < m; q += G) lists[i + q * lstride] = a.b.nlist[(size_t)q * NT + b0 + i];
+            }
+        }
+    } else {
+        builds = 1;
+#pragma unroll
+        for (int k = 0; k < BPT; ++k) {
+            const int i = grp + k * NG;
+            cnt[k] = 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) rref[k][c] = r[k][c];
+            if (!own[k]) continue;
+            cnt[k] = build_list<Real, G, PERIODIC>(i, n, BN[i] != 0, i > 0 && BN[i - 1] != 0, r[k], P, P + nmax,
+                                                   P + 2 * nmax, per, nd, rl2, gl, lists + i, lstride);
+        }
     }
     if (noise_lds) {
         // the G lanes of a bead share its M Philox draws instead of each lane drawing all
@@ -782,6 +829,25 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
         }
     }
 
+    // keep the lists for the next launch when they were (re)built in this one
+    if (builds > 0) {
+#pragma unroll
+        for (int k = 0; k < BPT; ++k) {
+            const int i = grp + k * NG;
+            if (!own[k]) continue;
+            const int gi = b0 + i;
+            if (gl == 0) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) a.b.rref[c * NT + gi] = rref[k][c];
+                a.b.ncount[gi] = cnt[k];
+            }
+            if (a.list_in_lds) {
+                const int m = cnt[k] < kNeighbourMax ? cnt[k] : kNeighbourMax;
+                for (int q = gl; q < m; q += G) a.b.nlist[(size_t)q * NT + gi] = lists[i + q * lstride];
+            }
+        }
+    }
+
     // write back, translocation count, centre of mass
     double acc[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -839,7 +905,6 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
         }
     }
     if (tid == 0) {
-        double* dg = a.b.diag + 8 * blockIdx.x;
         dg[0] = acc[0];
         if (dg[1] < 0.0 && (int)acc[0] == n) dg[1] = (double)(step + 1);
         dg[2] = acc[1] / n;
@@ -847,6 +912,7 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
         dg[4] = acc[3] / n;
         dg[5] = (double)(step + 1);
         dg[6] += (double)builds;
+        if (builds > 0) dg[7] = 1.0;
     }
     if (flags) atomicOr(&a.st->err, flags);
 }
