@@ -213,6 +213,15 @@ int lb_moments(lbmd_ctx* ctx, int replica, unsigned what, void* host_out, size_t
 /* Bytes lb_moments needs for (replica, what); 0 if invalid. */
 size_t lb_moments_bytes(const lbmd_ctx* ctx, int replica, unsigned what);
 
+/* LB_MOM_FIELDS or LB_MOM_POPULATIONS for the `count` consecutive nodes node0 ..
+ * node0 + count - 1 of one replica (linear index x + nx (y + ny z)), written to host_out
+ * as [4][count] or [19][count] doubles (caller-owned, at least 8 * ncomp * count bytes),
+ * for sampling boxes too large to copy whole.  Synchronises like lb_moments.  Returns
+ * LB_EINVAL for another `what` or a range outside the replica, LB_ESIZE for a short
+ * buffer, LB_EUNSTABLE (output still written) when the device error word is set. */
+int lb_moments_range(lbmd_ctx* ctx, int replica, unsigned what, long long node0, int count, void* host_out,
+                     size_t bytes);
+
 /* Lattice-kernel launch shape in use (threads per block). */
 int lb_block_size(const lbmd_ctx* ctx);
 

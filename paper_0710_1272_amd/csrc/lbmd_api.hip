@@ -903,6 +903,34 @@ int lb_moments(lbmd_ctx* ctx, int replica, unsigned what, void* host_out, size_t
     return LB_OK;
 }
 
+int lb_moments_range(lbmd_ctx* ctx, int replica, unsigned what, long long node0, int count, void* host_out,
+                     size_t bytes) {
+    if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+    Context& c = ctx->c;
+    if (replica < 0 || replica >= (int)c.reps.size()) return fail(LB_EINVAL, "replica out of range");
+    if (what != LB_MOM_FIELDS && what != LB_MOM_POPULATIONS) return fail(LB_EINVAL, "only fields or populations");
+    const Replica& R = c.reps[replica];
+    if (node0 < 0 || count < 0 || node0 + count > R.V) return fail(LB_EINVAL, "node range outside the replica");
+    const int ncomp = what == LB_MOM_FIELDS ? 4 : 19;
+    if (!host_out || bytes < (size_t)ncomp * count * sizeof(double))
+        return fail(LB_ESIZE, "need " + std::to_string((size_t)ncomp * count * sizeof(double)) + " bytes");
+    double* out = (double*)host_out;
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    const long long chunk = (long long)(c.stage_doubles / 19);
+    for (long long k0 = 0; k0 < count; k0 += chunk) {
+        const int cnt = (int)std::min<long long>(chunk, count - k0);
+        HIP_TRY(launch_gather(c, replica, c.pops[c.cur], ncomp == 4 ? 1 : 0, node0 + k0, cnt, c.d_stage, c.stream));
+        for (int k = 0; k < ncomp; ++k)
+            HIP_TRY(hipMemcpyAsync(out + (size_t)k * count + k0, c.d_stage + (size_t)k * cnt, cnt * sizeof(double),
+                                   hipMemcpyDeviceToHost, c.stream));
+    }
+    RunState st;
+    HIP_TRY(hipMemcpyAsync(&st, c.d_state, sizeof st, hipMemcpyDeviceToHost, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    if (st.err) return fail(LB_EUNSTABLE, "device error word " + std::to_string(st.err));
+    return LB_OK;
+}
+
 int lb_destroy(lbmd_ctx* ctx) {
     if (!ctx) return LB_OK;
     Context& c = ctx->c;

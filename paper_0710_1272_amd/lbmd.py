@@ -32,7 +32,7 @@ LB_ERR_BEAD_IN_SOLID, LB_ERR_BEAD_OUTSIDE, LB_ERR_NONFINITE, LB_ERR_BOND_STRETCH
     1, 2, 4, 8, 16)
 
 EXPORTED = ["lb_required_bytes", "lb_validate_config", "lb_init", "lb_step", "lb_couple", "md_step",
-            "lb_moments", "lb_moments_bytes", "lb_block_size", "lb_launch_shape", "lb_md_lanes", "lb_destroy",
+            "lb_moments", "lb_moments_bytes", "lb_moments_range", "lb_block_size", "lb_launch_shape", "lb_md_lanes", "lb_destroy",
             "lb_strerror", "lb_last_error_message"]
 
 
@@ -92,6 +92,8 @@ def lib():
         L.lb_couple.argtypes = [C.c_void_p, C.c_uint]
         L.md_step.argtypes = [C.c_void_p]
         L.lb_moments.argtypes = [C.c_void_p, C.c_int, C.c_uint, C.c_void_p, C.c_size_t]
+        L.lb_moments_range.argtypes = [C.c_void_p, C.c_int, C.c_uint, C.c_longlong, C.c_int, C.c_void_p,
+                                       C.c_size_t]
         L.lb_moments_bytes.argtypes = [C.c_void_p, C.c_int, C.c_uint]
         L.lb_moments_bytes.restype = C.c_size_t
         L.lb_block_size.argtypes = [C.c_void_p]
@@ -265,6 +267,25 @@ class Simulation:
 
     def fields(self, replica: int = 0, allow_unstable: bool = False):
         a = self._moments(replica, LB_MOM_FIELDS, allow_unstable).reshape(4, -1)
+        return a[0], a[1:4]
+
+    def _range(self, replica: int, what: int, node0: int, count: int, ncomp: int,
+               allow_unstable: bool) -> np.ndarray:
+        out = np.zeros((ncomp, count), dtype=np.float64)
+        rc = lib().lb_moments_range(self.ctx, replica, what, int(node0), int(count),
+                                    out.ctypes.data_as(C.c_void_p), out.nbytes)
+        if not (rc == LB_EUNSTABLE and allow_unstable):
+            _check(rc, "lb_moments_range")
+        return out
+
+    def populations_range(self, node0: int, count: int, replica: int = 0,
+                          allow_unstable: bool = False) -> np.ndarray:
+        """[19][count] populations of nodes node0 .. node0 + count - 1."""
+        return self._range(replica, LB_MOM_POPULATIONS, node0, count, 19, allow_unstable)
+
+    def fields_range(self, node0: int, count: int, replica: int = 0, allow_unstable: bool = False):
+        """(rho [count], u [3][count]) of nodes node0 .. node0 + count - 1."""
+        a = self._range(replica, LB_MOM_FIELDS, node0, count, 4, allow_unstable)
         return a[0], a[1:4]
 
     def beads(self, replica: int = 0, allow_unstable: bool = False):
