@@ -442,9 +442,11 @@ int autotune_md(Context& c) {
 
 void destroy_graphs(Context& c) {
     for (int k = 0; k < 2; ++k) {
-        if (c.graph_coupled[k]) (void)hipGraphExecDestroy(c.graph_coupled[k]);
-        if (c.graph_lb[k]) (void)hipGraphExecDestroy(c.graph_lb[k]);
-        c.graph_coupled[k] = c.graph_lb[k] = nullptr;
+        for (int par = 0; par < 2; ++par)
+            for (int len = 0; len <= Context::kGraphSteps; ++len) {
+                if (c.graphs[k][par][len]) (void)hipGraphExecDestroy(c.graphs[k][par][len]);
+                c.graphs[k][par][len] = nullptr;
+            }
     }
 }
 
@@ -454,6 +456,8 @@ void release(Context& c) {
     if (c.cap) (void)hipStreamDestroy(c.cap);
     if (c.ev_fork) (void)hipEventDestroy(c.ev_fork);
     if (c.ev_join) (void)hipEventDestroy(c.ev_join);
+    if (c.h_small) (void)hipHostFree(c.h_small);
+    c.h_small = nullptr;
     if (c.owns_buffers) {
         for (int k = 0; k < 2; ++k)
             if (c.pops[k]) (void)hipFree(c.pops[k]);
@@ -484,14 +488,14 @@ hipError_t enqueue_step(Context& c, bool coupled, int cur, hipStream_t main) {
     return launch_stream_collide(c, src, dst, true, main);
 }
 
-int build_graph(Context& c, bool coupled, int parity, hipGraphExec_t* out) {
+int build_graph(Context& c, bool coupled, int parity, int len, hipGraphExec_t* out) {
     hipGraph_t g = nullptr;
     // the caller's stream may be the null stream, which cannot be captured: capture on
     // a private stream; the instantiated graph is then launched on the caller's stream
     HIP_TRY(hipStreamBeginCapture(c.cap, hipStreamCaptureModeThreadLocal));
     int cur = parity;
     hipError_t e = hipSuccess;
-    for (int k = 0; k < c.graph_unroll && e == hipSuccess; ++k) {
+    for (int k = 0; k < len && e == hipSuccess; ++k) {
         e = enqueue_step(c, coupled, cur, c.cap);
         cur = 1 - cur;
     }
@@ -700,6 +704,9 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
     if ((rc = check(hipStreamCreateWithFlags(&c.cap, hipStreamNonBlocking), "capture stream"))) return bail(rc);
     if ((rc = check(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming), "event"))) return bail(rc);
     if ((rc = check(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming), "event"))) return bail(rc);
+    if ((rc = check(hipHostMalloc((void**)&c.h_small, 32 * sizeof(double), hipHostMallocDefault),
+                    "pinned staging")))
+        return bail(rc);
 
     rc = c.storage == LB_STORE_F64 ? setup_beads<double>(c, cfg) : setup_beads<float>(c, cfg);
     if (rc) return bail(rc);
@@ -725,16 +732,19 @@ int lb_step(lbmd_ctx* ctx, int n_steps, unsigned flags) {
     Context& c = ctx->c;
     const bool coupled = (flags & LB_STEP_COUPLED) != 0;
     int done = 0;
-    if (c.use_graph && n_steps >= c.graph_unroll) {
-        hipGraphExec_t* slot = coupled ? c.graph_coupled : c.graph_lb;
-        while (n_steps - done >= c.graph_unroll) {
-            if (!slot[c.cur]) {
-                int rc = build_graph(c, coupled, c.cur, &slot[c.cur]);
+    if (c.use_graph) {
+        // graphs of kGraphSteps steps, then one graph for the remainder (each length and
+        // buffer parity is captured once and kept)
+        while (done < n_steps) {
+            const int len = std::min(n_steps - done, (int)Context::kGraphSteps);
+            hipGraphExec_t& g = c.graphs[coupled ? 1 : 0][c.cur][len];
+            if (!g) {
+                int rc = build_graph(c, coupled, c.cur, len, &g);
                 if (rc) return rc;
             }
-            HIP_TRY(hipGraphLaunch(slot[c.cur], c.stream));
-            if (c.graph_unroll & 1) c.cur = 1 - c.cur;
-            done += c.graph_unroll;
+            HIP_TRY(hipGraphLaunch(g, c.stream));
+            if (len & 1) c.cur = 1 - c.cur;
+            done += len;
         }
     }
     for (; done < n_steps; ++done) {
@@ -847,12 +857,15 @@ int lb_moments(lbmd_ctx* ctx, int replica, unsigned what, void* host_out, size_t
     double* out = (double*)host_out;
     const Replica& R = c.reps[replica];
     const void* cur = c.pops[c.cur];
-    HIP_TRY(hipStreamSynchronize(c.stream));
+    // every read below is ordered on the context's stream after the queued steps; small
+    // results travel through pinned staging with the run state, one synchronisation
+    double* hs = c.h_small;
+    RunState* hst = (RunState*)(hs + 16);
     switch (what) {
         case LB_MOM_CONSERVED: {
             double* d_out4 = c.d_partials + 4 * (size_t)c.partial_blocks;
             HIP_TRY(launch_conserved(c, replica, cur, d_out4, c.stream));
-            HIP_TRY(hipMemcpyAsync(out, d_out4, 4 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+            HIP_TRY(hipMemcpyAsync(hs, d_out4, 4 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
             break;
         }
         case LB_MOM_FIELDS:
@@ -878,24 +891,21 @@ int lb_moments(lbmd_ctx* ctx, int replica, unsigned what, void* host_out, size_t
         case LB_MOM_TRANSLOC: {
             const double* diag = c.storage == LB_STORE_F64 ? ((BeadPtrs<double>*)c.bead_ptrs)->diag
                                                            : ((BeadPtrs<float>*)c.bead_ptrs)->diag;
-            double d[8];
-            HIP_TRY(hipMemcpyAsync(d, diag + 8 * replica, sizeof d, hipMemcpyDeviceToHost, c.stream));
-            HIP_TRY(hipStreamSynchronize(c.stream));
-            out[0] = d[0];
-            out[1] = d[1];
-            out[2] = d[2];
-            out[3] = d[3];
-            out[4] = d[4];
-            out[5] = (double)c.host_step;
+            HIP_TRY(hipMemcpyAsync(hs, diag + 8 * replica, 8 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
             break;
         }
         case LB_MOM_STATUS:
             break;
     }
-    RunState st;
-    HIP_TRY(hipMemcpyAsync(&st, c.d_state, sizeof st, hipMemcpyDeviceToHost, c.stream));
+    HIP_TRY(hipMemcpyAsync(hst, c.d_state, sizeof(RunState), hipMemcpyDeviceToHost, c.stream));
     HIP_TRY(hipStreamSynchronize(c.stream));
-    if (what == LB_MOM_STATUS) {
+    const RunState st = *hst;
+    if (what == LB_MOM_CONSERVED) {
+        for (int k = 0; k < 4; ++k) out[k] = hs[k];
+    } else if (what == LB_MOM_TRANSLOC) {
+        for (int k = 0; k < 5; ++k) out[k] = hs[k];
+        out[5] = (double)c.host_step;
+    } else if (what == LB_MOM_STATUS) {
         out[0] = (double)st.err;
         out[1] = (double)st.step;
     }

@@ -55,6 +55,7 @@ struct Context {
     void* beads = nullptr;
     void* work = nullptr;
     bool owns_buffers = false;
+    double* h_small = nullptr;         // pinned host staging for small read-outs (32 doubles)
     int cur = 0;                       // which pops buffer holds the current state
     long long host_step = 0;           // mirror of the device step counter
 
@@ -73,9 +74,9 @@ struct Context {
     int md_lanes = 0;                  // lanes per bead of the bead kernel (0: by bead count)
 
     bool use_graph = true;
-    hipGraphExec_t graph_coupled[2] = {nullptr, nullptr};  // by parity of cur
-    hipGraphExec_t graph_lb[2] = {nullptr, nullptr};
-    int graph_unroll = 8;
+    // instantiated graphs of 1..kGraphSteps steps, by (coupled, parity of cur, length)
+    static constexpr int kGraphSteps = 16;
+    hipGraphExec_t graphs[2][2][kGraphSteps + 1] = {};
 };
 
 // work-buffer layout (byte offsets), computed on the host
