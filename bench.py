@@ -206,6 +206,35 @@ def extra_workloads(steps_scale=1.0):
     return out
 
 
+def no_hydro(steps_scale=1.0):
+    """Beads alone in a fluid at rest (the no-solvent comparison of Sec. III) against the
+    coupled step, on the 512-replica translocation ensemble (48^3 boxes, N = 32)."""
+    import torch
+
+    from workloads import configs as WC
+
+    w = WC.ensemble48_n32(512, WC.ENSEMBLE_SEED_GPU, WC.STORE_F32)
+    log(f"no-solvent comparison on {w.name}")
+    sim = build_case(w, WC.STORE_F32)
+    n = int(200 * steps_scale)
+    res = {}
+    for hydro in (True, False):
+        sim.step(10, hydro=hydro)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(n, hydro=hydro)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res["coupled" if hydro else "no_solvent"] = {
+            "replica_steps_per_s": round(len(w.replicas) * n / dt, 1), "ms_per_step": round(dt / n * 1e3, 4)}
+    res["workload"] = w.name
+    res["speedup_without_solvent"] = round(res["no_solvent"]["replica_steps_per_s"]
+                                           / res["coupled"]["replica_steps_per_s"], 2)
+    sim.close()
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -288,6 +317,7 @@ def main():
     }
     if not args.no_extras:
         out["workloads"] = extra_workloads()
+        out["no_solvent"] = no_hydro()
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w)

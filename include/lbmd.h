@@ -172,15 +172,20 @@ int lb_validate_config(const lbmd_config* cfg);
  * Synchronises the stream before returning. */
 int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, lbmd_ctx** out);
 
-#define LB_STEP_COUPLED 1u /* steps 1-4 of Sec. II; without it: lattice update only */
+#define LB_STEP_COUPLED 1u  /* steps 1-4 of Sec. II; without it: lattice update only */
+#define LB_STEP_NO_HYDRO 2u /* beads only, in a fluid at rest (the no-solvent comparison of
+                               Sec. III): u_i = 0, no spreading, populations untouched */
 
 /* Enqueues n_steps LB time steps (Eq. lbe with Delta t = 1).  With
  * LB_STEP_COUPLED each step is: nearest-node velocity interpolation at the beads,
  * M MD substeps with that velocity frozen, then the lattice update with the
  * spread reaction force S_p = -(w_p / c_s^2) Fbar_i . c_p added after collision
  * at each bead's node (Fbar_i = mean over the substeps of drag + random force).
- * Without it, only the lattice stream-and-collide runs.  Asynchronous: returns
- * launch errors only. */
+ * Without it, only the lattice stream-and-collide runs.  With LB_STEP_NO_HYDRO
+ * (exclusive with LB_STEP_COUPLED) only the beads advance: M substeps with drag
+ * against u_i = 0 and the random force, no lattice update, no spreading; the step
+ * counter advances as for any step.  Asynchronous: returns launch errors, or
+ * LB_EINVAL for both flags together. */
 int lb_step(lbmd_ctx* ctx, int n_steps, unsigned flags);
 
 #define LB_COUPLE_INTERP 1u /* step 1 of Sec. II alone: u(x) -> u_i, nearest node of each bead */

@@ -314,10 +314,18 @@ class Sim:
     def n(self) -> int:
         return len(self.r)
 
-    def step(self, n_steps: int = 1, coupled: bool = True):
+    def step(self, n_steps: int = 1, coupled: bool = True, hydro: bool = True):
+        """n LB steps: coupled (Sec. II), lattice only, or, with hydro=False, the beads
+        alone in a fluid at rest (u = 0; the no-solvent comparison of Sec. III): the
+        populations are left as they are."""
         L = lib()
         for _ in range(n_steps):
-            if coupled and self.n > 0:
+            if not hydro:
+                if self.n > 0:
+                    _, fl = md_substeps(self.box, self.md, self.chain_len, self.r, self.v,
+                                        np.zeros((self.n, 3)), self.step_no, self.seed)
+                    self.flags |= fl
+            elif coupled and self.n > 0:
                 self.flags |= L.ora_coupled_step(
                     C.byref(self._b), C.byref(self._m), self.n, len(self.chain_len),
                     _ip(self.chain_len), _dp(self.f), _dp(self.S), _dp(self.work), _dp(self.r),

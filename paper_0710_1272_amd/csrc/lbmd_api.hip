@@ -441,7 +441,7 @@ int autotune_md(Context& c) {
 }
 
 void destroy_graphs(Context& c) {
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < 3; ++k) {
         for (int par = 0; par < 2; ++par)
             for (int len = 0; len <= Context::kGraphSteps; ++len) {
                 if (c.graphs[k][par][len]) (void)hipGraphExecDestroy(c.graphs[k][par][len]);
@@ -472,9 +472,16 @@ void release(Context& c) {
 }
 
 // enqueue one LB step on the context's streams (no graph)
-hipError_t enqueue_step(Context& c, bool coupled, int cur, hipStream_t main) {
+hipError_t enqueue_step(Context& c, int mode, int cur, hipStream_t main) {
     void* src = c.pops[cur];
     void* dst = c.pops[1 - cur];
+    if (mode == STEP_NO_HYDRO) {
+        // beads alone; the counter moves in its own launch, after every replica has read it
+        hipError_t e;
+        if (c.ntot_beads > 0 && (e = launch_md(c, src, MD_SUBSTEPS | MD_NO_HYDRO, main)) != hipSuccess) return e;
+        return launch_bump(c, main);
+    }
+    const bool coupled = mode == STEP_COUPLED;
     if (coupled && c.ntot_beads > 0) {
         hipError_t e;
         if ((e = hipEventRecord(c.ev_fork, main)) != hipSuccess) return e;
@@ -488,7 +495,7 @@ hipError_t enqueue_step(Context& c, bool coupled, int cur, hipStream_t main) {
     return launch_stream_collide(c, src, dst, true, main);
 }
 
-int build_graph(Context& c, bool coupled, int parity, int len, hipGraphExec_t* out) {
+int build_graph(Context& c, int mode, int parity, int len, hipGraphExec_t* out) {
     hipGraph_t g = nullptr;
     // the caller's stream may be the null stream, which cannot be captured: capture on
     // a private stream; the instantiated graph is then launched on the caller's stream
@@ -496,8 +503,8 @@ int build_graph(Context& c, bool coupled, int parity, int len, hipGraphExec_t* o
     int cur = parity;
     hipError_t e = hipSuccess;
     for (int k = 0; k < len && e == hipSuccess; ++k) {
-        e = enqueue_step(c, coupled, cur, c.cap);
-        cur = 1 - cur;
+        e = enqueue_step(c, mode, cur, c.cap);
+        if (mode != STEP_NO_HYDRO) cur = 1 - cur;
     }
     hipError_t e2 = hipStreamEndCapture(c.cap, &g);
     if (e != hipSuccess) {
@@ -730,26 +737,29 @@ int lb_step(lbmd_ctx* ctx, int n_steps, unsigned flags) {
     if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
     if (n_steps < 0) return fail(LB_EINVAL, "n_steps < 0");
     Context& c = ctx->c;
-    const bool coupled = (flags & LB_STEP_COUPLED) != 0;
+    if ((flags & LB_STEP_COUPLED) && (flags & LB_STEP_NO_HYDRO))
+        return fail(LB_EINVAL, "LB_STEP_COUPLED and LB_STEP_NO_HYDRO exclude each other");
+    const int mode = (flags & LB_STEP_COUPLED) ? STEP_COUPLED : (flags & LB_STEP_NO_HYDRO) ? STEP_NO_HYDRO : STEP_LB;
+    const bool flips = mode != STEP_NO_HYDRO;  // the populations change buffers
     int done = 0;
     if (c.use_graph) {
         // graphs of kGraphSteps steps, then one graph for the remainder (each length and
         // buffer parity is captured once and kept)
         while (done < n_steps) {
             const int len = std::min(n_steps - done, (int)Context::kGraphSteps);
-            hipGraphExec_t& g = c.graphs[coupled ? 1 : 0][c.cur][len];
+            hipGraphExec_t& g = c.graphs[mode][c.cur][len];
             if (!g) {
-                int rc = build_graph(c, coupled, c.cur, len, &g);
+                int rc = build_graph(c, mode, c.cur, len, &g);
                 if (rc) return rc;
             }
             HIP_TRY(hipGraphLaunch(g, c.stream));
-            if (len & 1) c.cur = 1 - c.cur;
+            if (flips && (len & 1)) c.cur = 1 - c.cur;
             done += len;
         }
     }
     for (; done < n_steps; ++done) {
-        HIP_TRY(enqueue_step(c, coupled, c.cur, c.stream));
-        c.cur = 1 - c.cur;
+        HIP_TRY(enqueue_step(c, mode, c.cur, c.stream));
+        if (flips) c.cur = 1 - c.cur;
     }
     c.host_step += n_steps;
     return LB_OK;

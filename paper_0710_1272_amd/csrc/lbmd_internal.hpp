@@ -23,7 +23,8 @@ struct MDDev {
     double f_drive;                   // signed along x
 };
 
-enum MDMode : int { MD_INTERP = 1, MD_SUBSTEPS = 2, MD_COUPLED = 3 };
+enum MDMode : int { MD_INTERP = 1, MD_SUBSTEPS = 2, MD_COUPLED = 3, MD_NO_HYDRO = 4 };
+enum StepMode : int { STEP_LB = 0, STEP_COUPLED = 1, STEP_NO_HYDRO = 2 };
 
 // Lattice-kernel launch description for one block size.
 struct LatticeLaunch {
@@ -76,7 +77,7 @@ struct Context {
     bool use_graph = true;
     // instantiated graphs of 1..kGraphSteps steps, by (coupled, parity of cur, length)
     static constexpr int kGraphSteps = 16;
-    hipGraphExec_t graphs[2][2][kGraphSteps + 1] = {};
+    hipGraphExec_t graphs[3][2][kGraphSteps + 1] = {};  // [StepMode][parity][length]
 };
 
 // work-buffer layout (byte offsets), computed on the host

@@ -454,7 +454,7 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
                 for (int c = 0; c < 3; ++c) a.b.u[c * NT + gi] = u[k][c];
             }
         }
-    } else {
+    } else if (!(a.mode & MD_NO_HYDRO)) {
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
             const int i = grp + k * NG;
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) u[k][c] = a.b.u[c * NT + b0 + i];
         }
-    }
+    }  // without hydrodynamics: u = 0 and no node (nothing is spread)
     if (!(a.mode & MD_SUBSTEPS)) return;
 #pragma unroll
     for (int k = 0; k < BPT; ++k) {

@@ -24,7 +24,7 @@ LB_CFG_NO_GRAPH, LB_CFG_AUTOTUNE = 1, 2
 LB_MAP_AUTO, LB_MAP_FLAT, LB_MAP_ROWS = 0, 1, 2
 LB_XCD_AUTO, LB_XCD_HARDWARE, LB_XCD_CONTIGUOUS = 0, -1, -2
 LB_BUF_POPS, LB_BUF_BEADS, LB_BUF_WORK = 0, 1, 2
-LB_STEP_COUPLED = 1
+LB_STEP_COUPLED, LB_STEP_NO_HYDRO = 1, 2
 LB_COUPLE_INTERP, LB_COUPLE_SPREAD = 1, 2
 (LB_MOM_CONSERVED, LB_MOM_FIELDS, LB_MOM_POPULATIONS, LB_MOM_BEADS, LB_MOM_TRANSLOC,
  LB_MOM_COUPLING, LB_MOM_STATUS) = 1, 2, 3, 4, 5, 6, 7
@@ -219,8 +219,11 @@ class Simulation:
         self.ctx = ctx
 
     # -- stepping -------------------------------------------------------------------------
-    def step(self, n: int = 1, coupled: bool = True):
-        _check(lib().lb_step(self.ctx, int(n), LB_STEP_COUPLED if coupled else 0), "lb_step")
+    def step(self, n: int = 1, coupled: bool = True, hydro: bool = True):
+        """n LB steps: coupled (default), lattice only (coupled=False), or beads only in a
+        fluid at rest (hydro=False)."""
+        flags = (LB_STEP_COUPLED if coupled else 0) if hydro else LB_STEP_NO_HYDRO
+        _check(lib().lb_step(self.ctx, int(n), flags), "lb_step")
 
     def couple(self, direction: int):
         _check(lib().lb_couple(self.ctx, int(direction)), "lb_couple")

@@ -4,9 +4,12 @@ Every event is one replica of the 48^3 pore box of workloads.configs.ensemble48_
 translocation set-up of Sec. III at a reduced size): a 32-bead chain grown from the pore mouth
 with its own seed, advanced by FP64 coupled oracle steps until every bead lies past the wall's
 mid-plane (the completion step t_done) or the step cap is reached (t_done = -1, censored).
+With --no-hydro the beads move alone in a fluid at rest (u = 0, no lattice, the no-solvent
+comparison of Sec. III) and the sample goes to transloc_pore48_n32_nohydro.txt.
 Only oracle/ and the seeded input generators of workloads/ are called.
 
     python tests/golden/make_transloc_ensemble.py --events 256 --jobs 8
+    python tests/golden/make_transloc_ensemble.py --events 512 --jobs 8 --no-hydro
 """
 from __future__ import annotations
 
@@ -19,11 +22,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "transloc_pore48_n32.txt")
+HERE = os.path.dirname(os.path.abspath(__file__))
 CHUNK = 50
 
 
-def _event(k: int):
+def _event(args):
+    k, hydro = args
     os.environ["OMP_NUM_THREADS"] = "1"
     import numpy as np
 
@@ -38,7 +42,7 @@ def _event(k: int):
                                    np.zeros((3, rep.box.nodes)))
     sim = O.Sim(rep.box, w.md, rep.chain_len, f0, beads, None, seed=rep.seed)
     while sim.t_done < 0 and sim.step_no < WC.ENSEMBLE_STEP_CAP:
-        sim.step(min(CHUNK, WC.ENSEMBLE_STEP_CAP - sim.step_no))
+        sim.step(min(CHUNK, WC.ENSEMBLE_STEP_CAP - sim.step_no), hydro=hydro)
     return rep.seed, sim.t_done, sim.flags
 
 
@@ -46,7 +50,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--events", type=int, default=256)
     ap.add_argument("--jobs", type=int, default=8)
+    ap.add_argument("--no-hydro", action="store_true")
     args = ap.parse_args()
+    hydro = not args.no_hydro
+    out = os.path.join(HERE, "transloc_pore48_n32.txt" if hydro else "transloc_pore48_n32_nohydro.txt")
     from multiprocessing import get_context
 
     from workloads import configs as WC
@@ -54,13 +61,16 @@ def main():
     t0 = time.time()
     rows = []
     with get_context("spawn").Pool(args.jobs) as pool:
-        for i, row in enumerate(pool.imap(_event, range(args.events))):
+        for i, row in enumerate(pool.imap(_event, [(k, hydro) for k in range(args.events)])):
             rows.append(row)
             print(f"event {i}: seed {row[0]} t_done {row[1]} flags {row[2]} "
                   f"({time.time() - t0:.0f} s)", flush=True)
     md = WC.MDParams()
-    with open(OUT, "w") as fh:
-        fh.write("# Translocation times of the FP64 oracle (coupled LB + bead steps, Sec. II-III).\n")
+    with open(out, "w") as fh:
+        fh.write("# Translocation times of the FP64 oracle (coupled LB + bead steps, Sec. II-III).\n"
+                 if hydro else
+                 "# Translocation times of the FP64 oracle, beads alone in a fluid at rest (u = 0, "
+                 "the no-solvent comparison of Sec. III).\n")
         fh.write("# Written by tests/golden/make_transloc_ensemble.py; inputs from workloads.configs."
                  "ensemble48_n32.\n")
         fh.write("# box 48^3, free-slip faces, tau=1, one wall x=22..24 with pore y,z=23..25; "
@@ -73,7 +83,7 @@ def main():
         fh.write("# seed t_done flags\n")
         for seed, t, fl in rows:
             fh.write(f"{seed} {t} {fl}\n")
-    print(f"wrote {OUT}: {len(rows)} events in {time.time() - t0:.0f} s")
+    print(f"wrote {out}: {len(rows)} events in {time.time() - t0:.0f} s")
 
 
 if __name__ == "__main__":

@@ -20,36 +20,48 @@ from tests.common import gpu_sim, log
 from workloads import configs as WC
 from workloads import generate as G
 
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "transloc_pore48_n32.txt")
+HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+GOLDEN = os.path.join(HERE, "transloc_pore48_n32.txt")
+GOLDEN_NO_HYDRO = os.path.join(HERE, "transloc_pore48_n32_nohydro.txt")
 N_GPU = 512
 CHECK_EVERY = 250
 
 
-def oracle_times() -> np.ndarray:
-    rows = np.loadtxt(GOLDEN, comments="#", dtype=np.int64, ndmin=2)
+def oracle_times(path=GOLDEN) -> np.ndarray:
+    rows = np.loadtxt(path, comments="#", dtype=np.int64, ndmin=2)
     assert np.all(rows[:, 2] == 0), "the oracle ensemble holds an event with error flags"
     return rows[:, 1]
 
 
-def test_oracle_ensemble_file():
+@pytest.mark.parametrize("path", [GOLDEN, GOLDEN_NO_HYDRO], ids=["coupled", "nohydro"])
+def test_oracle_ensemble_file(path):
     """The stored sample is complete, uncensored and drawn from the oracle seed range."""
-    rows = np.loadtxt(GOLDEN, comments="#", dtype=np.int64, ndmin=2)
+    rows = np.loadtxt(path, comments="#", dtype=np.int64, ndmin=2)
     assert len(rows) >= 64
     assert np.array_equal(rows[:, 0], WC.ENSEMBLE_SEED_ORACLE + np.arange(len(rows)))
     t = rows[:, 1]
     assert np.all(t > 0) and np.all(t < WC.ENSEMBLE_STEP_CAP)
 
 
+def test_solvent_speeds_translocation():
+    """The oracle's own samples: with the lattice solvent the chain crosses faster than
+    alone in a fluid at rest (Sec. III finds hydrodynamics speeds translocation)."""
+    a, b = oracle_times(GOLDEN), oracle_times(GOLDEN_NO_HYDRO)
+    se = np.sqrt(a.var(ddof=1) / len(a) + b.var(ddof=1) / len(b))
+    assert b.mean() - a.mean() > 3 * se
+
+
 @pytest.mark.gpu
-@pytest.mark.parametrize("storage", [WC.STORE_F64, WC.STORE_F32, WC.STORE_F16, WC.STORE_BF16],
-                         ids=["f64", "f32", "f16dev", "bf16dev"])
-def test_translocation_time_distribution(storage):
+@pytest.mark.parametrize("storage,hydro", [(WC.STORE_F64, True), (WC.STORE_F32, True), (WC.STORE_F16, True),
+                                           (WC.STORE_BF16, True), (WC.STORE_F32, False)],
+                         ids=["f64", "f32", "f16dev", "bf16dev", "nohydro"])
+def test_translocation_time_distribution(storage, hydro):
     from scipy import stats
 
-    t_ora = oracle_times()
+    t_ora = oracle_times(GOLDEN if hydro else GOLDEN_NO_HYDRO)
     w = WC.ensemble48_n32(N_GPU, WC.ENSEMBLE_SEED_GPU, storage)
-    log(f"ensemble {w.name} storage {WC.STORE_NAMES[storage]}: {N_GPU} replicas, "
-        f"cap {WC.ENSEMBLE_STEP_CAP} steps")
+    log(f"ensemble {w.name} storage {WC.STORE_NAMES[storage]}{'' if hydro else ' without solvent'}: "
+        f"{N_GPU} replicas, cap {WC.ENSEMBLE_STEP_CAP} steps")
     beads = np.concatenate(G.workload_beads(w))
     sim = gpu_sim(w.replicas, w.md, storage, beads=beads)
     try:
@@ -57,7 +69,7 @@ def test_translocation_time_distribution(storage):
         t_gpu = np.full(N_GPU, -1)
         while steps < WC.ENSEMBLE_STEP_CAP:
             n = min(CHECK_EVERY, WC.ENSEMBLE_STEP_CAP - steps)
-            sim.step(n)
+            sim.step(n, hydro=hydro)
             steps += n
             t_gpu = np.array([sim.transloc(r)["t_done"] for r in range(N_GPU)])
             log(f"  step {steps}: {int(np.sum(t_gpu >= 0))} of {N_GPU} events complete")

@@ -153,6 +153,30 @@ def test_c2_coupled_pointwise(storage, pop_tol, pos_tol):
     assert np.allclose(tr["com"], com, rtol=0, atol=pos_tol)
 
 
+@pytest.mark.parametrize("storage,pos_tol", [(F64, 1e-10), (F32, 1e-4)], ids=["f64", "f32"])
+def test_c2_no_hydro_pointwise(storage, pos_tol):
+    """Beads alone in a fluid at rest (the no-solvent comparison of Sec. III): 30 steps
+    of positions and velocities against the oracle; the populations are not touched."""
+    w = WC.c2_translocation(storage)
+    rep = w.replicas[0]
+    beads = G.replica_beads(rep, w.md)
+    ora = oracle_sim(rep, w.md, beads=beads, step0=5)
+    ora.step(HORIZON, hydro=False)
+    with gpu_sim([rep], w.md, storage, beads=beads, step0=5) as sim:
+        f0 = sim.populations()
+        sim.step(HORIZON, hydro=False)
+        r, v = sim.beads()
+        tr = sim.transloc()
+        err_word, step = sim.status()
+        f1 = sim.populations()
+    log(f"  no solvent, {HORIZON} steps: |dr| {np.max(np.abs(r - ora.r)):.2e} |dv| {np.max(np.abs(v - ora.v)):.2e}")
+    assert err_word == 0 and step == 5 + HORIZON
+    assert np.array_equal(f0, f1)
+    assert np.max(np.abs(r - ora.r)) < pos_tol
+    assert np.max(np.abs(v - ora.v)) < 100 * pos_tol
+    assert tr["n_t"] == O.transloc(rep.box, ora.r)[0]
+
+
 def test_coupling_halves_equal_coupled_step():
     w = WC.c2_translocation(F32)
     rep = w.replicas[0]
