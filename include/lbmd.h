@@ -230,10 +230,12 @@ int lb_moments_range(lbmd_ctx* ctx, int replica, unsigned what, long long node0,
 /* Lattice-kernel launch shape in use (threads per block). */
 int lb_block_size(const lbmd_ctx* ctx);
 
-/* Lattice-kernel launch shape in use: threads per block, LB_MAP_FLAT/ROWS and the XCD
- * tile order (LB_XCD_HARDWARE, LB_XCD_CONTIGUOUS or a chunk size).  Any pointer may be
- * NULL.  Returns LB_OK or LB_EINVAL for a NULL context. */
-int lb_launch_shape(const lbmd_ctx* ctx, int* block, int* mapping, int* xcd_order);
+/* Lattice-kernel launch shape in use: threads per block, LB_MAP_FLAT/ROWS, the XCD
+ * tile order (LB_XCD_HARDWARE, LB_XCD_CONTIGUOUS or a chunk size) and whether the
+ * populations are written with non-temporal stores (1: both buffers together exceed
+ * 160 MB, so they are streamed past the last-level cache; 0: they stay cached between
+ * steps).  Any pointer may be NULL.  Returns LB_OK or LB_EINVAL for a NULL context. */
+int lb_launch_shape(const lbmd_ctx* ctx, int* block, int* mapping, int* xcd_order, int* nt_stores);
 
 /* Lanes per bead of the bead kernel in use (1, 2, 4, 8 or 16; each bead's neighbour
  * loop is split over its lanes), 0 if no replica has beads, LB_EINVAL for a NULL

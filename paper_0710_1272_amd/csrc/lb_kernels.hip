@@ -258,7 +258,7 @@ __global__ __launch_bounds__(BLOCK) void k_stream_collide(const Replica* __restr
                                                           const typename Codec<S>::T* __restrict__ src,
                                                           typename Codec<S>::T* __restrict__ dst,
                                                           RunState* __restrict__ st, int bump_step,
-                                                          int xcd_chunk, int mapping) {
+                                                          int xcd_chunk, int mapping, int nt_stores) {
     using C = Codec<S>;
     using Rl = typename C::R;
     if (bump_step && blockIdx.x == 0 && threadIdx.x == 0) st->step += 1;
@@ -321,10 +321,19 @@ __global__ __launch_bounds__(BLOCK) void k_stream_collide(const Replica* __restr
 
     typename C::T* __restrict__ out = dst + R.pop_base + idx;
     const long long V = R.V;
-    for_pops([&](auto P) {
-        constexpr int p = decltype(P)::value;
-        __builtin_nontemporal_store(C::template store<p>(f[p]), out + (long long)p * V);
-    });
+    // non-temporal stores keep a box larger than the last-level cache from evicting the
+    // next step's sources; a box that fits it is better left cached for the next sweep
+    if (nt_stores) {
+        for_pops([&](auto P) {
+            constexpr int p = decltype(P)::value;
+            __builtin_nontemporal_store(C::template store<p>(f[p]), out + (long long)p * V);
+        });
+    } else {
+        for_pops([&](auto P) {
+            constexpr int p = decltype(P)::value;
+            out[(long long)p * V] = C::template store<p>(f[p]);
+        });
+    }
 }
 
 // ---------------------------------------------------------------------------------
@@ -506,7 +515,7 @@ static hipError_t launch_sc_t(const Context& c, const void* src, void* dst, bool
     using T = typename Codec<S>::T;
     hipLaunchKernelGGL((k_stream_collide<S, BLOCK>), dim3(c.lat.total_tiles), dim3(BLOCK), 0, s,
                        c.d_reps, c.lat.d_prefix, (int)c.reps.size(), (const T*)src, (T*)dst, c.d_state,
-                       bump ? 1 : 0, c.lat_chunk, c.lat.mapping);
+                       bump ? 1 : 0, c.lat_chunk, c.lat.mapping, c.lat_nt ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -706,6 +706,9 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
     else if (cfg->xcd_order == LB_XCD_CONTIGUOUS) c.lat_chunk = -1;
     else c.lat_chunk = cfg->xcd_order;
     if ((rc = set_lattice_shape(c, cfg->block_size ? cfg->block_size : 256))) return bail(rc);
+    // both population buffers within 160 MB stay in the 256 MB last-level cache between
+    // sweeps when stored normally; larger ones are streamed past it
+    c.lat_nt = 2.0 * (double)c.pop_elems * (double)store_size(c.storage) > 160e6;
 
     if ((rc = check(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking), "side stream"))) return bail(rc);
     if ((rc = check(hipStreamCreateWithFlags(&c.cap, hipStreamNonBlocking), "capture stream"))) return bail(rc);
@@ -801,9 +804,10 @@ size_t lb_moments_bytes(const lbmd_ctx* ctx, int replica, unsigned what) {
 
 int lb_block_size(const lbmd_ctx* ctx) { return ctx ? ctx->c.lat.block : 0; }
 
-int lb_launch_shape(const lbmd_ctx* ctx, int* block, int* mapping, int* xcd_order) {
+int lb_launch_shape(const lbmd_ctx* ctx, int* block, int* mapping, int* xcd_order, int* nt_stores) {
     if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
     const Context& c = ctx->c;
+    if (nt_stores) *nt_stores = c.lat_nt ? 1 : 0;
     if (block) *block = c.lat.block;
     if (mapping) *mapping = c.lat.mapping == 1 ? LB_MAP_ROWS : LB_MAP_FLAT;
     if (xcd_order) *xcd_order = c.lat_chunk < 0 ? LB_XCD_CONTIGUOUS : (c.lat_chunk == 0 ? LB_XCD_HARDWARE : c.lat_chunk);

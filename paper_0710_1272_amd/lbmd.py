@@ -97,7 +97,8 @@ def lib():
         L.lb_moments_bytes.argtypes = [C.c_void_p, C.c_int, C.c_uint]
         L.lb_moments_bytes.restype = C.c_size_t
         L.lb_block_size.argtypes = [C.c_void_p]
-        L.lb_launch_shape.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.lb_launch_shape.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                      C.POINTER(C.c_int)]
         L.lb_md_lanes.argtypes = [C.c_void_p]
         L.lb_destroy.argtypes = [C.c_void_p]
         L.lb_strerror.argtypes = [C.c_int]
@@ -236,10 +237,11 @@ class Simulation:
         return lib().lb_block_size(self.ctx)
 
     def launch_shape(self):
-        b, m, x = C.c_int(), C.c_int(), C.c_int()
-        _check(lib().lb_launch_shape(self.ctx, C.byref(b), C.byref(m), C.byref(x)), "lb_launch_shape")
+        b, m, x, nt = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        _check(lib().lb_launch_shape(self.ctx, C.byref(b), C.byref(m), C.byref(x), C.byref(nt)),
+               "lb_launch_shape")
         return {"block": b.value, "mapping": {LB_MAP_FLAT: "flat", LB_MAP_ROWS: "rows"}[m.value],
-                "xcd_order": x.value, "md_lanes": self.md_lanes}
+                "xcd_order": x.value, "nt_stores": bool(nt.value), "md_lanes": self.md_lanes}
 
     @property
     def md_lanes(self) -> int:
