@@ -251,14 +251,14 @@ __device__ __forceinline__ typename Codec<S>::R collide(typename Codec<S>::R* f,
 // Thread-to-node mappings of the lattice kernel.
 enum LatticeMapping { MAP_FLAT = 0, MAP_ROWS = 1 };
 
-template <int S, int BLOCK>
+template <int S, int BLOCK, bool NT>
 __global__ __launch_bounds__(BLOCK) void k_stream_collide(const Replica* __restrict__ reps,
                                                           const int* __restrict__ prefix,
                                                           int n_reps,
                                                           const typename Codec<S>::T* __restrict__ src,
                                                           typename Codec<S>::T* __restrict__ dst,
                                                           RunState* __restrict__ st, int bump_step,
-                                                          int xcd_chunk, int mapping, int nt_stores) {
+                                                          int xcd_chunk, int mapping) {
     using C = Codec<S>;
     using Rl = typename C::R;
     if (bump_step && blockIdx.x == 0 && threadIdx.x == 0) st->step += 1;
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(BLOCK) void k_stream_collide(const Replica* __restr
     const long long V = R.V;
     // non-temporal stores keep a box larger than the last-level cache from evicting the
     // next step's sources; a box that fits it is better left cached for the next sweep
-    if (nt_stores) {
+    if constexpr (NT) {
         for_pops([&](auto P) {
             constexpr int p = decltype(P)::value;
             __builtin_nontemporal_store(C::template store<p>(f[p]), out + (long long)p * V);
@@ -510,13 +510,19 @@ __global__ __launch_bounds__(256) void k_conserved_final(const double* __restric
 // ---------------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------------
+template <int S, int BLOCK, bool NT>
+static hipError_t launch_sc_n(const Context& c, const void* src, void* dst, bool bump, hipStream_t s) {
+    using T = typename Codec<S>::T;
+    hipLaunchKernelGGL((k_stream_collide<S, BLOCK, NT>), dim3(c.lat.total_tiles), dim3(BLOCK), 0, s,
+                       c.d_reps, c.lat.d_prefix, (int)c.reps.size(), (const T*)src, (T*)dst, c.d_state,
+                       bump ? 1 : 0, c.lat_chunk, c.lat.mapping);
+    return hipGetLastError();
+}
+
 template <int S, int BLOCK>
 static hipError_t launch_sc_t(const Context& c, const void* src, void* dst, bool bump, hipStream_t s) {
-    using T = typename Codec<S>::T;
-    hipLaunchKernelGGL((k_stream_collide<S, BLOCK>), dim3(c.lat.total_tiles), dim3(BLOCK), 0, s,
-                       c.d_reps, c.lat.d_prefix, (int)c.reps.size(), (const T*)src, (T*)dst, c.d_state,
-                       bump ? 1 : 0, c.lat_chunk, c.lat.mapping, c.lat_nt ? 1 : 0);
-    return hipGetLastError();
+    return c.lat_nt ? launch_sc_n<S, BLOCK, true>(c, src, dst, bump, s)
+                    : launch_sc_n<S, BLOCK, false>(c, src, dst, bump, s);
 }
 
 template <int S>
