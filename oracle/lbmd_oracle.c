@@ -100,9 +100,14 @@ typedef struct {
     double eps_w, sigma_w;    /* bead-wall WCA */
     double f_drive;           /* pulling force magnitude inside the pore */
     int drive_sign;           /* +1: along +x, -1: along -x */
+    int rigid;                /* 1: rigid bonds of length r0 (SHAKE/RATTLE), 0: harmonic bonds */
+    double kappa_phi;         /* angular term kappa_phi phi^2 / 2 between consecutive bonds */
+    double shake_tol;         /* rigid bonds: |s^2 - r0^2| <= shake_tol r0^2 */
+    int shake_iter;           /* rigid bonds: most Newton iterations per substep */
 } ora_md;
 
-enum { ORA_BEAD_IN_SOLID = 1, ORA_BEAD_OUTSIDE = 2, ORA_NONFINITE = 4, ORA_BOND_STRETCH = 8 };
+enum { ORA_BEAD_IN_SOLID = 1, ORA_BEAD_OUTSIDE = 2, ORA_NONFINITE = 4, ORA_BOND_STRETCH = 8,
+       ORA_CONSTRAINT = 32 };
 
 static long node_index(const ora_box* b, int x, int y, int z)
 {
@@ -509,18 +514,57 @@ static int bonded_to_next(int i, int n_chains, const int* chain_len)
     return 0;
 }
 
-/* Conservative forces at the given positions: harmonic bonds, WCA between
- * all non-bonded pairs, WCA against the nearest solid surface and against
- * the free-slip faces.  F is [n][3] and is overwritten.  Returns flags. */
+/* Angular term of the angle-potential equation at bead i (chain neighbours i-1 and
+ * i+1): phi is the angle between the consecutive bonds d1 = r_i - r_{i-1} and
+ * d2 = r_{i+1} - r_i (0 for a straight chain), V = kappa_phi phi^2 / 2.  Adds -grad V to
+ * F of the three beads and returns V.  With c = cos(phi) = d1.d2 / (|d1||d2|):
+ * dV/dr_{i-1} = -kappa phi / sin(phi) * (-dc/dd1), dV/dr_{i+1} = ... (dc/dd2),
+ * and bead i takes minus the sum; phi / sin(phi) -> 1 as phi -> 0. */
+static double angle_term(const ora_box* b, const ora_md* md, const double* r, int i, double* F)
+{
+    double d1[3], d2[3];
+    displacement(b, r + 3 * i, r + 3 * (i - 1), d1);
+    displacement(b, r + 3 * (i + 1), r + 3 * i, d2);
+    double l1 = sqrt(d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2]);
+    double l2 = sqrt(d2[0] * d2[0] + d2[1] * d2[1] + d2[2] * d2[2]);
+    double dot = d1[0] * d2[0] + d1[1] * d2[1] + d1[2] * d2[2];
+    double cr[3] = {d1[1] * d2[2] - d1[2] * d2[1], d1[2] * d2[0] - d1[0] * d2[2], d1[0] * d2[1] - d1[1] * d2[0]};
+    double cross = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+    double phi = atan2(cross, dot);
+    double s = cross / (l1 * l2);
+    double phi_over_sin = s > 1e-8 ? phi / s : 1.0 + phi * phi / 6.0;
+    double c = dot / (l1 * l2);
+    double k = md->kappa_phi * phi_over_sin;
+    for (int a = 0; a < 3; ++a) {
+        double dc1 = d2[a] / (l1 * l2) - c * d1[a] / (l1 * l1); /* d cos / d d1 */
+        double dc2 = d1[a] / (l1 * l2) - c * d2[a] / (l2 * l2); /* d cos / d d2 */
+        double fa = -k * dc1;                                   /* force on i-1 */
+        double fc = k * dc2;                                    /* force on i+1 */
+        F[3 * (i - 1) + a] += fa;
+        F[3 * (i + 1) + a] += fc;
+        F[3 * i + a] -= fa + fc;
+    }
+    return 0.5 * md->kappa_phi * phi * phi;
+}
+
+/* Conservative forces at the given positions: harmonic bonds (when the bonds are
+ * not rigid), the angular term, WCA between all non-bonded pairs, WCA against the
+ * nearest solid surface and against the free-slip faces.  F is [n][3] and is
+ * overwritten.  Returns flags. */
 int ora_conservative_forces(const ora_box* b, const ora_md* md, int n, int n_chains,
                             const int* chain_len, const double* r, double* F)
 {
     int flags = 0;
     int nn[3] = {b->nx, b->ny, b->nz};
     memset(F, 0, sizeof(double) * 3 * (size_t)n);
-    /* bonds */
+    /* angular term between consecutive bonds */
+    if (md->kappa_phi != 0.0)
+        for (int i = 1; i + 1 < n; ++i)
+            if (bonded_to_next(i - 1, n_chains, chain_len) && bonded_to_next(i, n_chains, chain_len))
+                angle_term(b, md, r, i, F);
+    /* bonds (rigid bonds carry no potential: their forces are the constraint reactions) */
     for (int i = 0; i + 1 < n; ++i) {
-        if (!bonded_to_next(i, n_chains, chain_len)) continue;
+        if (md->rigid || !bonded_to_next(i, n_chains, chain_len)) continue;
         double d[3];
         displacement(b, r + 3 * (i + 1), r + 3 * i, d); /* from i to i+1 */
         double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
@@ -579,8 +623,15 @@ double ora_potential_energy(const ora_box* b, const ora_md* md, int n, int n_cha
 {
     double E = 0.0;
     int nn[3] = {b->nx, b->ny, b->nz};
+    if (md->kappa_phi != 0.0) {
+        double* junk = (double*)calloc(3 * (size_t)n, sizeof(double));
+        for (int i = 1; i + 1 < n; ++i)
+            if (bonded_to_next(i - 1, n_chains, chain_len) && bonded_to_next(i, n_chains, chain_len))
+                E += angle_term(b, md, r, i, junk);
+        free(junk);
+    }
     for (int i = 0; i + 1 < n; ++i) {
-        if (!bonded_to_next(i, n_chains, chain_len)) continue;
+        if (md->rigid || !bonded_to_next(i, n_chains, chain_len)) continue;
         double d[3];
         displacement(b, r + 3 * (i + 1), r + 3 * i, d);
         double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
@@ -610,6 +661,135 @@ double ora_potential_energy(const ora_box* b, const ora_md* md, int n, int n_cha
     return E;
 }
 
+/* Tridiagonal solve by the Thomas algorithm: a[k] x[k-1] + bd[k] x[k] + c[k] x[k+1] = d[k]
+ * for k = 0..m-1 (a[0], c[m-1] unused).  The solution overwrites d; bd and c are clobbered. */
+static void thomas(int m, const double* a, double* bd, double* c, double* d)
+{
+    for (int k = 1; k < m; ++k) {
+        double w = a[k] / bd[k - 1];
+        bd[k] -= w * c[k - 1];
+        d[k] -= w * d[k - 1];
+    }
+    d[m - 1] /= bd[m - 1];
+    for (int k = m - 2; k >= 0; --k) d[k] = (d[k] - c[k] * d[k + 1]) / bd[k];
+}
+
+/* Rigid bonds: the N-1 holonomic constraints of Sec. II, enforced on positions by
+ * SHAKE and on velocities by RATTLE.  Bond k joins beads k and k+1 of one chain; the
+ * rows of the other k are identities.
+ * Positions: r'_i = u_i + (lam_k d_k - lam_{k-1} d_{k-1}) / m, with u the unconstrained
+ * positions and d_k = r_k - r_{k+1} the bond vectors at the start of the substep; the
+ * multipliers solve |s_k|^2 = r0^2, s_k = r'_k - r'_{k+1}, by Newton iterations (the
+ * Jacobian is tridiagonal: dg_k/dlam_k = 4 s_k.d_k/m, dg_k/dlam_{k+-1} = -2 s_k.d_{k+-1}/m)
+ * until every |s_k^2 - r0^2| <= shake_tol r0^2.
+ * Velocities: v_i = (r'_i - r_i) / h, then v_i += (mu_k s_k - mu_{k-1} s_{k-1}) / m with
+ * the mu solving (v_k - v_{k+1}) . s_k = 0 for every bond (one tridiagonal solve), so the
+ * relative velocity of bonded beads is orthogonal to their separation.
+ * u is replaced by r'; v receives the constrained velocities.  Returns ORA_CONSTRAINT if
+ * the Newton iterations did not converge. */
+int ora_shake_rattle(const ora_box* b, const ora_md* md, int n, int n_chains, const int* chain_len,
+                     const double* r_old, double* u, double* v, double h)
+{
+    if (n < 2) {
+        for (int i = 0; i < 3 * n; ++i) v[i] = (u[i] - r_old[i]) / h;
+        return 0;
+    }
+    const int m = n - 1;
+    const double im = 1.0 / md->mass, b2 = md->r0 * md->r0;
+    double* d = (double*)calloc(3 * (size_t)m, sizeof(double));   /* reference bond vectors */
+    double* sv = (double*)calloc(3 * (size_t)m, sizeof(double));  /* current bond vectors */
+    double* lam = (double*)calloc((size_t)m, sizeof(double));
+    double* A = (double*)calloc((size_t)m, sizeof(double));
+    double* B = (double*)calloc((size_t)m, sizeof(double));
+    double* Cc = (double*)calloc((size_t)m, sizeof(double));
+    double* R = (double*)calloc((size_t)m, sizeof(double));
+    double* r = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    int* on = (int*)calloc((size_t)m, sizeof(int));
+    for (int k = 0; k < m; ++k) {
+        on[k] = bonded_to_next(k, n_chains, chain_len);
+        if (on[k]) displacement(b, r_old + 3 * k, r_old + 3 * (k + 1), d + 3 * k);
+    }
+    int flags = ORA_CONSTRAINT;
+    for (int it = 0; it <= md->shake_iter; ++it) {
+        /* positions for the current multipliers and the constraint residuals */
+        for (int i = 0; i < n; ++i)
+            for (int a = 0; a < 3; ++a) {
+                double x = u[3 * i + a];
+                if (i < m && on[i]) x += im * lam[i] * d[3 * i + a];
+                if (i > 0 && on[i - 1]) x -= im * lam[i - 1] * d[3 * (i - 1) + a];
+                r[3 * i + a] = x;
+            }
+        double worst = 0.0;
+        for (int k = 0; k < m; ++k) {
+            if (!on[k]) continue;
+            displacement(b, r + 3 * k, r + 3 * (k + 1), sv + 3 * k);
+            double g = sv[3 * k] * sv[3 * k] + sv[3 * k + 1] * sv[3 * k + 1] + sv[3 * k + 2] * sv[3 * k + 2] - b2;
+            worst = fmax(worst, fabs(g));
+            R[k] = -g;
+        }
+        if (worst <= md->shake_tol * b2) {
+            flags = 0;
+            break;
+        }
+        if (it == md->shake_iter) break;
+        for (int k = 0; k < m; ++k) {
+            if (!on[k]) {
+                A[k] = Cc[k] = 0.0;
+                B[k] = 1.0;
+                R[k] = 0.0;
+                continue;
+            }
+            const double* sk = sv + 3 * k;
+            B[k] = 4.0 * im * (sk[0] * d[3 * k] + sk[1] * d[3 * k + 1] + sk[2] * d[3 * k + 2]);
+            A[k] = (k > 0 && on[k - 1])
+                       ? -2.0 * im * (sk[0] * d[3 * (k - 1)] + sk[1] * d[3 * (k - 1) + 1] + sk[2] * d[3 * (k - 1) + 2])
+                       : 0.0;
+            Cc[k] = (k + 1 < m && on[k + 1])
+                        ? -2.0 * im * (sk[0] * d[3 * (k + 1)] + sk[1] * d[3 * (k + 1) + 1] + sk[2] * d[3 * (k + 1) + 2])
+                        : 0.0;
+        }
+        thomas(m, A, B, Cc, R);
+        for (int k = 0; k < m; ++k) lam[k] += R[k];
+    }
+    for (int i = 0; i < 3 * n; ++i) {
+        v[i] = (r[i] - r_old[i]) / h;
+        u[i] = r[i];
+    }
+    /* RATTLE: relative velocities of bonded beads orthogonal to their separations */
+    for (int k = 0; k < m; ++k) {
+        if (!on[k]) {
+            A[k] = Cc[k] = 0.0;
+            B[k] = 1.0;
+            R[k] = 0.0;
+            continue;
+        }
+        displacement(b, r + 3 * k, r + 3 * (k + 1), sv + 3 * k);
+        const double* sk = sv + 3 * k;
+        double rel = 0.0;
+        for (int a = 0; a < 3; ++a) rel += (v[3 * k + a] - v[3 * (k + 1) + a]) * sk[a];
+        R[k] = -rel;
+        B[k] = 2.0 * im * (sk[0] * sk[0] + sk[1] * sk[1] + sk[2] * sk[2]);
+        A[k] = 0.0;
+        Cc[k] = 0.0;
+    }
+    for (int k = 0; k < m; ++k) {
+        if (!on[k]) continue;
+        const double* sk = sv + 3 * k;
+        if (k > 0 && on[k - 1])
+            A[k] = -im * (sk[0] * sv[3 * (k - 1)] + sk[1] * sv[3 * (k - 1) + 1] + sk[2] * sv[3 * (k - 1) + 2]);
+        if (k + 1 < m && on[k + 1])
+            Cc[k] = -im * (sk[0] * sv[3 * (k + 1)] + sk[1] * sv[3 * (k + 1) + 1] + sk[2] * sv[3 * (k + 1) + 2]);
+    }
+    thomas(m, A, B, Cc, R);
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) {
+            if (i < m && on[i]) v[3 * i + a] += im * R[i] * sv[3 * i + a];
+            if (i > 0 && on[i - 1]) v[3 * i + a] -= im * R[i - 1] * sv[3 * (i - 1) + a];
+        }
+    free(d); free(sv); free(lam); free(A); free(B); free(Cc); free(R); free(r); free(on);
+    return flags;
+}
+
 /* Step 2: M molecular-dynamics substeps of length h = 1/M with the fluid
  * velocity u_i frozen (Sec. II).  Per substep, every force is evaluated at the
  * positions of the start of the substep:
@@ -617,9 +797,11 @@ double ora_potential_energy(const ora_box* b, const ora_md* md, int n, int n_cha
  *   F_drag = -m gamma (v - u_i)                 (drag eq.)
  *   F_r    = A (c0, c1, c2),  A = sqrt(24 m gamma kT / h), c uniform in [-1/2,1/2)
  *   F_drive = f_drive x-hat inside the pore (Sec. III)
- * then v += (h/m) F; r += h v.  Fbar accumulates (F_drag + F_r)/M, the force
- * whose reaction the fluid receives.  Philox counter = (bead, step, substep, 1),
- * key = (seed low word, seed high word). Returns error flags. */
+ * then v += (h/m) F; r += h v, and with rigid bonds SHAKE/RATTLE (ora_shake_rattle)
+ * on the new positions and velocities.  Fbar accumulates (F_drag + F_r)/M, the force
+ * whose reaction the fluid receives (constraint reactions are internal).  Philox
+ * counter = (bead, step, substep, 1), key = (seed low word, seed high word). Returns
+ * error flags. */
 int ora_md_substeps(const ora_box* b, const ora_md* md, int n, int n_chains, const int* chain_len,
                     double* r, double* v, const double* u, double* fbar, uint32_t step,
                     uint64_t seed)
@@ -629,6 +811,7 @@ int ora_md_substeps(const ora_box* b, const ora_md* md, int n, int n_chains, con
     const double A = sqrt(24.0 * md->mass * md->gamma * md->kT / h);
     int flags = 0;
     double* F = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    double* r0 = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
     uint32_t key[2] = {(uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32)};
     for (int i = 0; i < 3 * n; ++i) fbar[i] = 0.0;
     for (int k = 0; k < M; ++k) {
@@ -646,13 +829,16 @@ int ora_md_substeps(const ora_box* b, const ora_md* md, int n, int n_chains, con
                 fbar[3 * i + a] += (drag + noise) / M;
             }
         }
+        if (md->rigid) memcpy(r0, r, sizeof(double) * 3 * (size_t)n);
         for (int i = 0; i < n; ++i)
             for (int a = 0; a < 3; ++a) {
                 v[3 * i + a] += h / md->mass * F[3 * i + a];
                 r[3 * i + a] += h * v[3 * i + a];
             }
+        if (md->rigid) flags |= ora_shake_rattle(b, md, n, n_chains, chain_len, r0, r, v, h);
     }
     free(F);
+    free(r0);
     return flags;
 }
 

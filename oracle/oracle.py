@@ -42,7 +42,8 @@ class _MD(C.Structure):
     _fields_ = [("M", C.c_int), ("mass", C.c_double), ("gamma", C.c_double), ("kT", C.c_double),
                 ("k_bond", C.c_double), ("r0", C.c_double), ("eps", C.c_double),
                 ("sigma", C.c_double), ("eps_w", C.c_double), ("sigma_w", C.c_double),
-                ("f_drive", C.c_double), ("drive_sign", C.c_int)]
+                ("f_drive", C.c_double), ("drive_sign", C.c_int), ("rigid", C.c_int),
+                ("kappa_phi", C.c_double), ("shake_tol", C.c_double), ("shake_iter", C.c_int)]
 
 
 _lib = None
@@ -80,6 +81,7 @@ def lib():
         L.ora_md_substeps.argtypes = [bp, mp, C.c_int, C.c_int, ip, dp, dp, dp, dp, C.c_uint32,
                                       C.c_uint64]
         L.ora_transloc.argtypes = [bp, C.c_int, dp, dp]
+        L.ora_shake_rattle.argtypes = [bp, mp, C.c_int, C.c_int, ip, dp, dp, dp, C.c_double]
         L.ora_coupled_step.argtypes = [bp, mp, C.c_int, C.c_int, ip, dp, dp, dp, dp, dp, dp, dp,
                                        lp, C.c_uint32, C.c_uint64]
         L.ora_lattice.argtypes = [ip, dp, ip]
@@ -279,6 +281,18 @@ def md_substeps(box, md, chain_len, r, v, u, step: int, seed: int):
     flags = lib().ora_md_substeps(C.byref(b), C.byref(m), n, len(cl), _ip(cl), _dp(r), _dp(v),
                                   _dp(np.ascontiguousarray(u)), _dp(fbar), step & 0xFFFFFFFF, seed)
     return fbar, flags
+
+
+def shake_rattle(box, md, chain_len, r_old, u, h: float):
+    """Rigid-bond projection of one substep: (r', v, flags) from the start-of-substep
+    positions r_old and the unconstrained positions u."""
+    cl = np.ascontiguousarray(chain_len, dtype=np.int32)
+    r_new = np.ascontiguousarray(u, dtype=np.float64).copy()
+    v = np.zeros_like(r_new)
+    b, m = make_box(box), make_md(md)
+    fl = lib().ora_shake_rattle(C.byref(b), C.byref(m), len(r_new), len(cl), _ip(cl),
+                                _dp(np.ascontiguousarray(r_old, dtype=np.float64)), _dp(r_new), _dp(v), h)
+    return r_new, v, fl
 
 
 def transloc(box, r: np.ndarray):

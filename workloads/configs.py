@@ -63,6 +63,19 @@ class MDParams:
     sigma_w: float = 0.9
     f_drive: float = 0.02
     drive_sign: int = 1
+    rigid: int = 0             # 1: rigid bonds of length r0 (SHAKE/RATTLE), k_bond unused
+    kappa_phi: float = 0.0     # angular term between consecutive bonds
+    shake_tol: float = 1e-12   # rigid bonds: |s^2 - r0^2| <= shake_tol r0^2
+    shake_iter: int = 30       # rigid bonds: most Newton iterations per substep
+
+
+def paper_polymer(**kw) -> MDParams:
+    """The bead model of Sec. II-III itself: rigid bonds b = 1.2 (SHAKE/RATTLE), M = 5,
+    eps = 2e-3, sigma = 1.8, gamma = 0.1, kT = 1/beta = 1e-4, F_drive = 0.02.  The paper
+    gives no kappa_phi: 0 unless set."""
+    base = dict(M=5, rigid=1, eps=2e-3, eps_w=2e-3, kappa_phi=0.0)
+    base.update(kw)
+    return MDParams(**base)
 
 
 @dataclass
