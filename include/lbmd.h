@@ -53,6 +53,7 @@ extern "C" {
 #define LB_ERR_NONFINITE 4u       /* a bead coordinate is not finite */
 #define LB_ERR_BOND_STRETCH 8u    /* a bond is longer than 2 r0 */
 #define LB_ERR_DENSITY 16u        /* a fluid node met rho <= 0 or a non-finite rho */
+#define LB_ERR_CONSTRAINT 32u     /* rigid bonds: SHAKE did not converge in shake_iter iterations */
 
 /* ---- configuration ---------------------------------------------------------- */
 #define LB_BC_PERIODIC 0
@@ -97,6 +98,14 @@ typedef struct lbmd_md_params {
     double eps_w, sigma_w; /* WCA on the distance to the nearest solid surface / free-slip face */
     double f_drive;    /* pulling force on beads whose nearest node is a pore node */
     int drive_sign;    /* +1: along +x; -1: along -x */
+    int rigid;         /* 0: harmonic bonds (k_bond, r0); 1: rigid bonds of length r0, the
+                          N-1 holonomic constraints of Sec. II, enforced on positions by
+                          SHAKE (Newton iterations) and on velocities by RATTLE; at most
+                          512 beads per replica */
+    double kappa_phi;  /* angular term kappa_phi phi^2 / 2 between consecutive bonds (>= 0) */
+    double shake_tol;  /* rigid bonds: |s^2 - r0^2| <= shake_tol r0^2 for every bond */
+    int shake_iter;    /* rigid bonds: most Newton iterations per substep; not converging
+                          sets LB_ERR_CONSTRAINT */
 } lbmd_md_params;
 
 /* Optional initial state (host arrays, read during lb_init only). */

@@ -20,6 +20,7 @@ _SRC = os.path.join(_HERE, "lbmd_oracle.c")
 _LIB = os.path.join(_HERE, "liblbmd_oracle.so")
 
 Q = 19
+ERR_CONSTRAINT = 32  # rigid bonds: SHAKE did not converge within shake_iter iterations
 
 
 def build(force: bool = True) -> str:

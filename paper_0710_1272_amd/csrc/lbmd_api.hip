@@ -202,9 +202,16 @@ int lb_validate_config(const lbmd_config* cfg) {
             !std::isfinite(m.f_drive))
             return fail(LB_EINVAL, "md parameters out of range");
         if (m.drive_sign != 1 && m.drive_sign != -1) return fail(LB_EINVAL, "md.drive_sign must be +-1");
-        // kick-drift is stable for omega h < 2; the stiffest chain mode has omega = 2 sqrt(k/m)
-        if (2.0 * std::sqrt(m.k_bond / m.mass) / m.M >= 2.0)
+        if (m.rigid != 0 && m.rigid != 1) return fail(LB_EINVAL, "md.rigid must be 0 or 1");
+        if (!(m.kappa_phi >= 0) || !std::isfinite(m.kappa_phi)) return fail(LB_EINVAL, "md.kappa_phi must be >= 0");
+        if (m.rigid) {
+            if (!(m.shake_tol > 0) || m.shake_iter < 1)
+                return fail(LB_EINVAL, "rigid bonds need shake_tol > 0 and shake_iter >= 1");
+            if (max_beads > 512) return fail(LB_EINVAL, "rigid bonds: at most 512 beads per replica");
+        } else if (2.0 * std::sqrt(m.k_bond / m.mass) / m.M >= 2.0) {
+            // kick-drift is stable for omega h < 2; the stiffest chain mode has omega = 2 sqrt(k/m)
             return fail(LB_EINVAL, "bond stiffness unstable at this M: need 2 sqrt(k/m)/M < 2");
+        }
         if (!cfg->init || !cfg->init->bead_r) return fail(LB_EINVAL, "beads need init->bead_r");
     }
     return LB_OK;
@@ -620,6 +627,11 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
     md.rl2 = (std::sqrt(md.rc2) + skin + 1e-3) * (std::sqrt(md.rc2) + skin + 1e-3);
     md.half_skin2 = 0.25 * skin * skin;
     md.f_drive = m.drive_sign * m.f_drive;
+    md.rigid = m.rigid;
+    md.shake_iter = m.shake_iter;
+    md.kappa_phi = m.kappa_phi;
+    md.b2 = m.r0 * m.r0;
+    md.shake_tol_b2 = m.shake_tol * md.b2;
 
     // buffers
     const size_t pop_bytes = lb_required_bytes(cfg, LB_BUF_POPS);

@@ -21,6 +21,10 @@ struct MDDev {
     double eps_w, sigma_w2, rcw2, rcw; // WCA bead-surface
     double rl2, half_skin2;           // Verlet list radius^2 (rc + skin)^2 and (skin/2)^2
     double f_drive;                   // signed along x
+    int rigid;                        // rigid bonds (SHAKE/RATTLE) instead of harmonic ones
+    int shake_iter;
+    double kappa_phi;                 // angular term between consecutive bonds
+    double b2, shake_tol_b2;          // rigid bond length^2 and the SHAKE tolerance on |s^2 - b^2|
 };
 
 enum MDMode : int { MD_INTERP = 1, MD_SUBSTEPS = 2, MD_COUPLED = 3, MD_NO_HYDRO = 4 };

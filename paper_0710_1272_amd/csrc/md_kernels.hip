@@ -302,6 +302,78 @@ __device__ __forceinline__ Real separation(const double* ri, const double* PX, c
     return separation_v<Real, PERIODIC>(ri, pj, per, nd, d);
 }
 
+// Angular term of Sec. II at the middle bead of (a, b, c): V = kappa phi^2 / 2 with phi
+// the angle between the consecutive bonds d1 = r_b - r_a and d2 = r_c - r_b (0 for a
+// straight chain).  With cos(phi) = d1.d2 / (|d1||d2|), the forces are
+// f_a = -kappa (phi / sin phi) dcos/dd1, f_c = kappa (phi / sin phi) dcos/dd2, and the
+// middle bead takes -(f_a + f_c); phi / sin phi -> 1 as phi -> 0.
+template <class Real, bool PERIODIC>
+__device__ __forceinline__ void angle_forces(const double* ra, const double* rb, const double* rc, const int* per,
+                                             const double* nd, Real kappa, Real* fa, Real* fc) {
+    Real d1[3], d2[3];
+    const Real q1 = separation_v<Real, PERIODIC>(rb, ra, per, nd, d1);
+    const Real q2 = separation_v<Real, PERIODIC>(rc, rb, per, nd, d2);
+    const Real l1 = sqrt(q1), l2 = sqrt(q2);
+    const Real dot = d1[0] * d2[0] + d1[1] * d2[1] + d1[2] * d2[2];
+    const Real cx = d1[1] * d2[2] - d1[2] * d2[1], cy = d1[2] * d2[0] - d1[0] * d2[2],
+               cz = d1[0] * d2[1] - d1[1] * d2[0];
+    const Real cross = sqrt(cx * cx + cy * cy + cz * cz);
+    const Real phi = atan2(cross, dot);
+    const Real il12 = Real(1) / (l1 * l2);
+    const Real sn = cross * il12;
+    const Real small = sizeof(Real) == 4 ? Real(1e-4) : Real(1e-8);
+    const Real phi_over_sin = sn > small ? phi / sn : Real(1) + phi * phi / Real(6);
+    const Real c = dot * il12;
+    const Real kk = kappa * phi_over_sin;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        fa[a] = -kk * (d2[a] * il12 - c * d1[a] / q1);
+        fc[a] = kk * (d1[a] * il12 - c * d2[a] / q2);
+    }
+}
+
+// One tridiagonal system a_t x_{t-1} + b_t x_t + c_t x_{t+1} = d_t per workgroup, row t
+// held by thread t (t < m), solved by parallel cyclic reduction: at stride s each row
+// eliminates its couplings to rows t - s and t + s (rows outside 0..m-1 are identities),
+// so after ceil(log2 m) levels x_t = d_t / b_t.  Double-buffered in LDS (W: [2][4][nmax]
+// doubles: a, b, c, d); one barrier per level.  Every thread of the block must call it.
+__device__ __forceinline__ double pcr_solve(double* W, int nmax, int m, int t, double a, double b, double c,
+                                            double d) {
+    const bool row = t < m;
+    int buf = 0;
+    if (row) {
+        W[(0 * 4 + 0) * nmax + t] = a;
+        W[(0 * 4 + 1) * nmax + t] = b;
+        W[(0 * 4 + 2) * nmax + t] = c;
+        W[(0 * 4 + 3) * nmax + t] = d;
+    }
+    __syncthreads();
+    for (int s = 1; s < m; s <<= 1) {
+        const double* Ws = W + buf * 4 * nmax;
+        double* Wd = W + (buf ^ 1) * 4 * nmax;
+        if (row) {
+            const int lo = t - s, hi = t + s;
+            const double al = lo >= 0 ? Ws[lo] : 0.0, bl = lo >= 0 ? Ws[nmax + lo] : 1.0;
+            const double cl = lo >= 0 ? Ws[2 * nmax + lo] : 0.0, dl = lo >= 0 ? Ws[3 * nmax + lo] : 0.0;
+            const double ah = hi < m ? Ws[hi] : 0.0, bh = hi < m ? Ws[nmax + hi] : 1.0;
+            const double ch = hi < m ? Ws[2 * nmax + hi] : 0.0, dh = hi < m ? Ws[3 * nmax + hi] : 0.0;
+            const double k1 = a / bl, k2 = c / bh;
+            const double na = -al * k1, nc = -ch * k2;
+            b = b - cl * k1 - ah * k2;
+            d = d - dl * k1 - dh * k2;
+            a = na;
+            c = nc;
+            Wd[t] = a;
+            Wd[nmax + t] = b;
+            Wd[2 * nmax + t] = c;
+            Wd[3 * nmax + t] = d;
+        }
+        buf ^= 1;
+        __syncthreads();
+    }
+    return row ? d / b : 0.0;
+}
+
 // Verlet-list entries each lane keeps in registers (slot s of lane gl is entry gl + s G);
 // entries beyond them are read from the list
 // (fewer under the 1024-thread bound, where registers are scarcer)
@@ -398,6 +470,15 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
                                      : (unsigned char*)(BN + nmax));
     const bool noise_lds = G > 1 && a.noise_in_lds;
     const MDDev md = a.md;
+    // rigid bonds: SHAKE/RATTLE work area after the random-force table, doubles:
+    // reference bond vectors [3][nmax], multipliers [nmax], velocities [3][nmax], and
+    // the cyclic-reduction buffers [2][4][nmax]
+    double* RW = (double*)((unsigned char*)NZ +
+                           (noise_lds ? (size_t)md.M * 3 * nmax * sizeof(Real) : (size_t)0));
+    double* SDV = RW;
+    double* LAM = RW + 3 * nmax;
+    double* VXV = RW + 4 * nmax;
+    double* PCRW = RW + 7 * nmax;
     const int M = md.M;
     const long long step = a.st->step;
     const int* nn = GM.n;
@@ -576,13 +657,18 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
     }
 
     // chain neighbours (constant over the step) and the register slots of the lists
-    bool bnk[BPT], bpk[BPT];
+    bool bnk[BPT], bpk[BPT], bnn[BPT], bpp[BPT];  // bonded to i+1, i-1, and i+1 to i+2, i-1 to i-2
 #pragma unroll
     for (int k = 0; k < BPT; ++k) {
         const int i = grp + k * NG;
         bnk[k] = own[k] && BN[i] != 0;
         bpk[k] = own[k] && i > 0 && BN[i - 1] != 0;
+        bnn[k] = bnk[k] && BN[i + 1] != 0;
+        bpp[k] = bpk[k] && i > 1 && BN[i - 2] != 0;
     }
+    // rigid chains (at most 512 beads, one bond row per thread) only run with one bead per group
+    const bool rigid = BPT == 1 && md.rigid != 0;
+    const Real kappa = (Real)md.kappa_phi;
     constexpr int K = SlotsPerLane<G, BPT, MAXT>::K;
     int slot[BPT][K], nslot[BPT];
     // Beads within reach of a wall slab or a free-slip face.  Decided at each list build
@@ -714,13 +800,35 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
             // absent neighbour is the bead itself and adds 0
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
-                const bool on = side == 0 ? bpk[k] : bnk[k];
+                const bool on = (side == 0 ? bpk[k] : bnk[k]) && !rigid;
                 Real d[3];
                 const Real b2 = separation_v<Real, PERIODIC>(r[k], side == 0 ? pm : pp, per, nd, d);
                 if (on && b2 > Real(4) * r0 * r0) flags |= LB_ERR_BOND_STRETCH;
                 const Real coef = on ? -kb * (Real(1) - r0 * fast_rsqrt<Real>(b2)) : Real(0);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) F[k][c] += coef * d[c];
+            }
+            // angular terms centred on i - 1, i and i + 1 (each needs both of its bonds)
+            if (kappa != Real(0) && (bpk[k] || bnk[k])) {
+                const int jmm = bpp[k] ? i - 2 : i, jpp = bnn[k] ? i + 2 : i;
+                const double pmm[3] = {PX[jmm], PY[jmm], PZ[jmm]};
+                const double ppp[3] = {PX[jpp], PY[jpp], PZ[jpp]};
+                Real fa[3], fc[3];
+                if (bpk[k] && bnk[k]) {
+                    angle_forces<Real, PERIODIC>(pm, r[k], pp, per, nd, kappa, fa, fc);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) F[k][c] -= fa[c] + fc[c];
+                }
+                if (bpp[k]) {
+                    angle_forces<Real, PERIODIC>(pmm, pm, r[k], per, nd, kappa, fa, fc);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) F[k][c] += fc[c];
+                }
+                if (bnn[k]) {
+                    angle_forces<Real, PERIODIC>(r[k], pp, ppp, per, nd, kappa, fa, fc);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) F[k][c] += fa[c];
+                }
             }
             if (!(isfinite(r[k][0]) && isfinite(r[k][1]) && isfinite(r[k][2]))) flags |= LB_ERR_NONFINITE;
             // nearest solid surface over the walls (min, earlier wall on ties) and the pore
@@ -786,24 +894,151 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
         }
         // kick-drift into the other position buffer; the single barrier below both
         // publishes the new positions and collects the rebuild vote
-        int moved = 0;
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
             const int i = grp + k * NG;
             if (!own[k]) continue;
-            Real disp2 = 0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 v[k][c] += hm * F[k][c];
                 r[k][c] += (double)(h * v[k][c]);
-                const Real dd = (Real)(r[k][c] - rref[k][c]);
-                disp2 += dd * dd;
             }
-            moved |= !(disp2 <= hs2);  // also catches a non-finite position
             if (gl == 0) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) QX[c * nmax + i] = r[k][c];
             }
+        }
+        if (rigid) {
+            // SHAKE and RATTLE on the unconstrained positions now in QX (PX still holds
+            // the positions of the start of the substep); row t of the bond systems is
+            // thread t, bond t joining beads t and t + 1
+            __syncthreads();
+            const int m = n - 1, t = tid;
+            const bool on = t < m && BN[t] != 0;
+            const double ih = 1.0 / md.h, im = md.inv_mass;
+            double dref[3] = {0.0, 0.0, 0.0}, ut[3] = {0.0, 0.0, 0.0}, ut1[3] = {0.0, 0.0, 0.0};
+            if (on) {
+                const double pa[3] = {PX[t], PY[t], PZ[t]}, pb[3] = {PX[t + 1], PY[t + 1], PZ[t + 1]};
+                (void)separation_v<double, PERIODIC>(pa, pb, per, nd, dref);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    ut[c] = QX[c * nmax + t];
+                    ut1[c] = QX[c * nmax + t + 1];
+                }
+            }
+            if (t < nmax) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) SDV[c * nmax + t] = dref[c];
+                LAM[t] = 0.0;
+            }
+            __syncthreads();
+            // Newton iterations on the multipliers: positions r'_i = u_i + (lam_i d_i -
+            // lam_{i-1} d_{i-1})/m, residuals g_t = |r'_t - r'_{t+1}|^2 - b^2
+            double dm1[3] = {0.0, 0.0, 0.0}, dp1[3] = {0.0, 0.0, 0.0};
+            if (on) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    dm1[c] = t > 0 ? SDV[c * nmax + t - 1] : 0.0;
+                    dp1[c] = t + 1 < m ? SDV[c * nmax + t + 1] : 0.0;
+                }
+            }
+            for (int it = 0;; ++it) {
+                double sv[3] = {0.0, 0.0, 0.0}, g = 0.0;
+                if (on) {
+                    const double lm = t > 0 ? LAM[t - 1] : 0.0, l0 = LAM[t], lp = t + 1 < m ? LAM[t + 1] : 0.0;
+                    double ra[3], rb[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        ra[c] = ut[c] + im * (l0 * dref[c] - lm * dm1[c]);
+                        rb[c] = ut1[c] + im * (lp * dp1[c] - l0 * dref[c]);
+                    }
+                    g = (double)separation_v<double, PERIODIC>(ra, rb, per, nd, sv) - md.b2;
+                }
+                const bool bad = on && !(fabs(g) <= md.shake_tol_b2);
+                if (!__syncthreads_or(bad)) break;
+                if (it >= md.shake_iter) {
+                    flags |= LB_ERR_CONSTRAINT;
+                    break;
+                }
+                const double B = on ? 4.0 * im * (sv[0] * dref[0] + sv[1] * dref[1] + sv[2] * dref[2]) : 1.0;
+                const double Aa = on ? -2.0 * im * (sv[0] * dm1[0] + sv[1] * dm1[1] + sv[2] * dm1[2]) : 0.0;
+                const double Cc = on ? -2.0 * im * (sv[0] * dp1[0] + sv[1] * dp1[1] + sv[2] * dp1[2]) : 0.0;
+                const double x = pcr_solve(PCRW, nmax, m, t, Aa, B, Cc, on ? -g : 0.0);
+                if (on) LAM[t] += x;
+                __syncthreads();
+            }
+            // constrained positions and velocities (v = (r' - r) / h) of every bead
+#pragma unroll
+            for (int k = 0; k < BPT; ++k) {
+                const int i = grp + k * NG;
+                if (!own[k]) continue;
+                const double li = bnk[k] ? LAM[i] : 0.0, lm = bpk[k] ? LAM[i - 1] : 0.0;
+                const double r_old[3] = {PX[i], PY[i], PZ[i]};
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double di = bnk[k] ? SDV[c * nmax + i] : 0.0, dmi = bpk[k] ? SDV[c * nmax + i - 1] : 0.0;
+                    r[k][c] += im * (li * di - lm * dmi);
+                    v[k][c] = (Real)((r[k][c] - r_old[c]) * ih);
+                }
+            }
+            __syncthreads();  // every read of the multipliers and of QX is done
+#pragma unroll
+            for (int k = 0; k < BPT; ++k) {
+                const int i = grp + k * NG;
+                if (!own[k] || gl != 0) continue;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    QX[c * nmax + i] = r[k][c];
+                    VXV[c * nmax + i] = (double)v[k][c];
+                }
+            }
+            __syncthreads();
+            // RATTLE: (v'_t - v'_{t+1}) . s_t = 0 with v'_i = v_i + (mu_i s_i - mu_{i-1} s_{i-1})/m
+            {
+                double st[3] = {0.0, 0.0, 0.0}, sm[3] = {0.0, 0.0, 0.0}, sp[3] = {0.0, 0.0, 0.0};
+                double rel = 0.0;
+                auto bondvec = [&](int j, double* out) {  // r'_j - r'_{j+1}
+                    const double pa[3] = {QX[j], QX[nmax + j], QX[2 * nmax + j]};
+                    const double pb[3] = {QX[j + 1], QX[nmax + j + 1], QX[2 * nmax + j + 1]};
+                    (void)separation_v<double, PERIODIC>(pa, pb, per, nd, out);
+                };
+                if (on) {
+                    bondvec(t, st);
+                    if (t > 0 && BN[t - 1]) bondvec(t - 1, sm);
+                    if (t + 1 < m && BN[t + 1]) bondvec(t + 1, sp);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) rel += (VXV[c * nmax + t] - VXV[c * nmax + t + 1]) * st[c];
+                }
+                const double B = on ? 2.0 * im * (st[0] * st[0] + st[1] * st[1] + st[2] * st[2]) : 1.0;
+                const double Aa = on ? -im * (st[0] * sm[0] + st[1] * sm[1] + st[2] * sm[2]) : 0.0;
+                const double Cc = on ? -im * (st[0] * sp[0] + st[1] * sp[1] + st[2] * sp[2]) : 0.0;
+                const double mu = pcr_solve(PCRW, nmax, m, t, Aa, B, Cc, on ? -rel : 0.0);
+                if (t < nmax) LAM[t] = on ? mu : 0.0;
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < BPT; ++k) {
+                    const int i = grp + k * NG;
+                    if (!own[k]) continue;
+                    double si[3] = {0.0, 0.0, 0.0}, sim[3] = {0.0, 0.0, 0.0};
+                    if (bnk[k]) bondvec(i, si);
+                    if (bpk[k]) bondvec(i - 1, sim);
+                    const double mi = bnk[k] ? LAM[i] : 0.0, mm = bpk[k] ? LAM[i - 1] : 0.0;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) v[k][c] = (Real)(VXV[c * nmax + i] + im * (mi * si[c] - mm * sim[c]));
+                }
+            }
+        }
+        int moved = 0;
+#pragma unroll
+        for (int k = 0; k < BPT; ++k) {
+            if (!own[k]) continue;
+            Real disp2 = 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const Real dd = (Real)(r[k][c] - rref[k][c]);
+                disp2 += dd * dd;
+            }
+            moved |= !(disp2 <= hs2);  // also catches a non-finite position
         }
         const int vb = sub & 1;
         const bool wave_moved = __ballot(moved) != 0ull;
@@ -974,6 +1209,8 @@ static int md_nmax(const Context& c) { return (c.max_beads + 63) / 64 * 64; }
 static constexpr size_t kMDLdsBudget = 150 * 1024;
 
 static size_t md_base_lds(size_t nmax) { return nmax * (6 * sizeof(double) + sizeof(int) + 1); }
+// SHAKE/RATTLE work area of rigid chains: 15 doubles per bead, always in LDS
+static size_t md_rigid_lds(const Context& c, size_t nmax) { return c.md.rigid ? nmax * 15 * sizeof(double) : 0; }
 static size_t md_list_lds(size_t nmax) { return nmax * kNeighbourMax * sizeof(unsigned short); }
 static size_t md_noise_lds(const Context& c, size_t nmax) {
     return (size_t)c.md.M * 3 * nmax * (c.storage == LB_STORE_F64 ? sizeof(double) : sizeof(float));
@@ -982,20 +1219,20 @@ static size_t md_noise_lds(const Context& c, size_t nmax) {
 // Verlet lists go to LDS when positions (two buffers), node/bond arrays and lists fit
 static bool md_lists_in_lds(const Context& c) {
     const size_t nmax = (size_t)md_nmax(c);
-    return md_base_lds(nmax) + md_list_lds(nmax) <= kMDLdsBudget;
+    return md_base_lds(nmax) + md_rigid_lds(c, nmax) + md_list_lds(nmax) <= kMDLdsBudget;
 }
 
 // the per-step table of random forces, when several lanes share a bead and it fits
 static bool md_noise_in_lds(const Context& c, int G) {
     const size_t nmax = (size_t)md_nmax(c);
-    size_t b = md_base_lds(nmax) + md_noise_lds(c, nmax);
+    size_t b = md_base_lds(nmax) + md_rigid_lds(c, nmax) + md_noise_lds(c, nmax);
     if (md_lists_in_lds(c)) b += md_list_lds(nmax);
     return G > 1 && b <= kMDLdsBudget;
 }
 
 static size_t md_lds_bytes(const Context& c, int G) {
     const size_t nmax = (size_t)md_nmax(c);
-    size_t b = md_base_lds(nmax);
+    size_t b = md_base_lds(nmax) + md_rigid_lds(c, nmax);
     if (md_lists_in_lds(c)) b += md_list_lds(nmax);
     if (md_noise_in_lds(c, G)) b += md_noise_lds(c, nmax);
     return b;

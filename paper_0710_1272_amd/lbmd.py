@@ -30,6 +30,7 @@ LB_COUPLE_INTERP, LB_COUPLE_SPREAD = 1, 2
  LB_MOM_COUPLING, LB_MOM_STATUS) = 1, 2, 3, 4, 5, 6, 7
 LB_ERR_BEAD_IN_SOLID, LB_ERR_BEAD_OUTSIDE, LB_ERR_NONFINITE, LB_ERR_BOND_STRETCH, LB_ERR_DENSITY = (
     1, 2, 4, 8, 16)
+LB_ERR_CONSTRAINT = 32
 
 EXPORTED = ["lb_required_bytes", "lb_validate_config", "lb_init", "lb_step", "lb_couple", "md_step",
             "lb_moments", "lb_moments_bytes", "lb_moments_range", "lb_block_size", "lb_launch_shape", "lb_md_lanes", "lb_destroy",
@@ -52,7 +53,8 @@ class lbmd_md_params(C.Structure):
     _fields_ = [("M", C.c_int), ("mass", C.c_double), ("gamma", C.c_double), ("kT", C.c_double),
                 ("k_bond", C.c_double), ("r0", C.c_double), ("eps", C.c_double),
                 ("sigma", C.c_double), ("eps_w", C.c_double), ("sigma_w", C.c_double),
-                ("f_drive", C.c_double), ("drive_sign", C.c_int)]
+                ("f_drive", C.c_double), ("drive_sign", C.c_int), ("rigid", C.c_int),
+                ("kappa_phi", C.c_double), ("shake_tol", C.c_double), ("shake_iter", C.c_int)]
 
 
 class lbmd_initial_state(C.Structure):

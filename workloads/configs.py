@@ -140,6 +140,14 @@ def c2_translocation(storage: int = STORE_F32) -> Workload:
                     20000, "128x64x64 D3Q19 BGK tau=1, 3x3 pore wall, N=100 chain, M=20")
 
 
+def c2_paper_polymer(storage: int = STORE_F32) -> Workload:
+    """The 128 x 64 x 64 / N=100 set-up with the paper's own bead model: rigid bonds,
+    M = 5 substeps, eps = eps_w = 2e-3."""
+    box = pore_box(128, 64, 64)
+    return Workload("pore128x64x64_n100_rigid", [Replica(box, [100], BASE_SEED)], paper_polymer(), storage,
+                    20000, "128x64x64 D3Q19 BGK tau=1, 3x3 pore wall, N=100 rigid chain (SHAKE/RATTLE), M=5")
+
+
 def c3_translocation(storage: int = STORE_F16) -> Workload:
     box = pore_box(256, 128, 128)
     return Workload("pore256x128x128_n400", [Replica(box, [400], BASE_SEED)], MDParams(), storage,
