@@ -29,7 +29,13 @@
  *   - random force: uniform, centred, variance 2 m gamma kT / h per component,
  *     drawn from Philox4x32-10 (Salmon et al., SC'11) keyed by the replica seed;
  *   - WCA bead-bead repulsion, bonded neighbours excluded; harmonic bonds;
- *     WCA wall repulsion on the distance to the nearest solid surface.
+ *     WCA wall repulsion on the distance to the nearest solid surface;
+ *   - thermal source F_p (the paper gives no formula and cites the fluctuating LB of
+ *     Adhikari et al.): noise on every non-conserved mode of the collision with the
+ *     covariance that keeps the populations at their equilibrium fluctuations
+ *     <df_p df_q> = mu rho w_p delta_pq, mu = kT / c_s^2 (Duenweg, Schiller and Ladd's
+ *     fluctuation-dissipation condition for one BGK relaxation rate); uniform variates
+ *     of unit variance drawn from Philox keyed by the replica seed.
  */
 #include <math.h>
 #include <stdint.h>
@@ -90,6 +96,7 @@ typedef struct {
     int wall[2][6];  /* x0,x1: solid planes x0..x1; y0,y1,z0,z1: open pore (empty if y0>y1) */
     double tau;      /* BGK relaxation time, omega = 1/tau (Delta t = 1) */
     double rho0;     /* reference density */
+    double kT;       /* temperature of the thermal source F_p; 0: F_p = 0 */
 } ora_box;
 
 typedef struct {
@@ -202,15 +209,53 @@ static void node_moments(const double* fp, double* rho, double* j)
     j[2] = jz;
 }
 
+void ora_philox(const uint32_t* ctr_in, const uint32_t* key_in, uint32_t* out);
+static double sym_uniform(uint32_t r);
+
+/* Thermal source F_p of Eq. lbe at one fluid node, for the BGK collision with the
+ * single rate omega (gamma = 1 - omega is the factor by which the collision scales
+ * every non-conserved mode).  Fluctuation-dissipation asks for noise of covariance
+ *     <F_p F_q> = mu rho (1 - gamma^2) (Pi W)_pq,   W = diag(w),  mu = kT / c_s^2,
+ * where Pi removes the conserved density and momentum parts (so that the collision
+ * keeps conserving them):  (Pi x)_p = x_p - w_p (sum_q x_q + c_p . sum_q c_q x_q / c_s^2).
+ * Drawn as F = phi Pi eta with eta_p = sqrt(w_p) xi_p and xi_p independent of zero mean
+ * and unit variance (then Cov(Pi eta) = Pi W Pi^T = Pi W); phi = sqrt(mu rho (1-gamma^2)).
+ * xi_p = sqrt(12) U_p, U_p the symmetric uniforms of Philox words 4k..4k+3 of counters
+ * (node, step, k, 2), k = 0..4, key = the replica seed; rho = the pre-collision density. */
+static void thermal_source(const ora_box* b, long node, double rho, uint32_t step, uint64_t seed, double* F)
+{
+    const double omega = 1.0 / b->tau, gamma = 1.0 - omega;
+    const double mu = b->kT / CS2;
+    const double phi = sqrt(mu * rho * (1.0 - gamma * gamma));
+    uint32_t key[2] = {(uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32)};
+    double eta[20];
+    for (int k = 0; k < 5; ++k) {
+        uint32_t ctr[4] = {(uint32_t)node, step, (uint32_t)k, 2u}, rnd[4];
+        ora_philox(ctr, key, rnd);
+        for (int a = 0; a < 4; ++a) eta[4 * k + a] = sqrt(12.0) * sym_uniform(rnd[a]);
+    }
+    double s0 = 0.0, s1[3] = {0.0, 0.0, 0.0};
+    for (int p = 0; p < Q; ++p) {
+        eta[p] *= sqrt(weight(p));
+        s0 += eta[p];
+        for (int a = 0; a < 3; ++a) s1[a] += CV[p][a] * eta[p];
+    }
+    for (int p = 0; p < Q; ++p) {
+        const double cs = CV[p][0] * s1[0] + CV[p][1] * s1[1] + CV[p][2] * s1[2];
+        F[p] = phi * (eta[p] - weight(p) * (s0 + cs / CS2));
+    }
+}
+
 /* Lattice layout shared as a data format with the callers: population p of
  * node (x,y,z) lives at f[p*V + x + nx*(y + ny*z)].  Solid nodes hold zero. */
 
-/* One LB time step, Eq. lbe with F_p = 0 and Delta t = 1:
- *   f_p(x + c_p, t+1) = f_p(x,t) - omega (f_p - f_p^eq)(x,t) + S_p(x,t)
- * f: pre-collision populations at t (in), at t+1 (out).  S: source or NULL.
- * work: scratch of 19*V doubles. Returns the number of fluid nodes whose
- * density was not positive and finite. */
-long ora_lb_step(const ora_box* b, double* f, double* work, const double* S)
+/* One LB time step, Eq. lbe with Delta t = 1:
+ *   f_p(x + c_p, t+1) = f_p(x,t) - omega (f_p - f_p^eq)(x,t) + F_p(x,t) + S_p(x,t)
+ * F_p: the thermal source above when b->kT > 0 (its random numbers indexed by `step`
+ * and keyed by `seed`), else 0.  f: pre-collision populations at t (in), at t+1 (out).
+ * S: source or NULL.  work: scratch of 19*V doubles. Returns the number of fluid
+ * nodes whose density was not positive and finite. */
+long ora_lb_step(const ora_box* b, double* f, double* work, const double* S, uint32_t step, uint64_t seed)
 {
     const long V = (long)b->nx * b->ny * b->nz;
     const double omega = 1.0 / b->tau;
@@ -230,8 +275,10 @@ long ora_lb_step(const ora_box* b, double* f, double* work, const double* S)
                 u[1] = j[1] / rho;
                 u[2] = j[2] / rho;
                 ora_feq(rho, u, feq);
+                double F[Q] = {0.0};
+                if (b->kT > 0.0) thermal_source(b, i, rho, step, seed, F);
                 for (int q = 0; q < Q; ++q) {
-                    double post = fp[q] - omega * (fp[q] - feq[q]);
+                    double post = fp[q] - omega * (fp[q] - feq[q]) + F[q];
                     if (S) post += S[(long)q * V + i];
                     int t[4];
                     ora_push_target(b, x, y, z, q, t);
@@ -349,6 +396,13 @@ void ora_philox(const uint32_t* ctr_in, const uint32_t* key_in, uint32_t* out)
 static double centred(uint32_t r)
 {
     return (double)(int32_t)(r & 0xFFFFFF00u) * (1.0 / 4294967296.0);
+}
+
+/* symmetric uniform in (-1/2, 1/2): the top 24 bits as k, (k + 1/2) / 2^24 - 1/2; mean 0,
+ * variance (1 - 2^-48) / 12 */
+static double sym_uniform(uint32_t r)
+{
+    return ((double)(r >> 8) + 0.5) * (1.0 / 16777216.0) - 0.5;
 }
 
 /* ---------------------------------------------------------------------------
@@ -880,7 +934,7 @@ int ora_coupled_step(const ora_box* b, const ora_md* md, int n, int n_chains, co
     int flags = ora_md_substeps(b, md, n, n_chains, chain_len, r, v, u, fbar, step, seed);
     memset(S, 0, sizeof(double) * Q * (size_t)V);
     ora_spread(b, n, node, fbar, S);
-    if (ora_lb_step(b, f, work, S) > 0) flags |= 16;
+    if (ora_lb_step(b, f, work, S, step, seed) > 0) flags |= 16;
     return flags;
 }
 

@@ -36,7 +36,7 @@ def build(force: bool = True) -> str:
 class _Box(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("bc", C.c_int * 3),
                 ("n_walls", C.c_int), ("wall", (C.c_int * 6) * 2), ("tau", C.c_double),
-                ("rho0", C.c_double)]
+                ("rho0", C.c_double), ("kT", C.c_double)]
 
 
 class _MD(C.Structure):
@@ -66,7 +66,7 @@ def lib():
         L.ora_is_pore.argtypes = [bp, C.c_int, C.c_int, C.c_int]
         L.ora_push_target.argtypes = [bp, C.c_int, C.c_int, C.c_int, C.c_int, ip]
         L.ora_feq.argtypes = [C.c_double, dp, dp]
-        L.ora_lb_step.argtypes = [bp, dp, dp, dp]
+        L.ora_lb_step.argtypes = [bp, dp, dp, dp, C.c_uint32, C.c_uint64]
         L.ora_lb_step.restype = C.c_long
         L.ora_add_streamed_source.argtypes = [bp, dp, dp]
         L.ora_fields.argtypes = [bp, dp, dp, dp]
@@ -118,6 +118,7 @@ def make_box(box) -> _Box:
             b.wall[k][m] = int(w[m])
     b.tau = float(box.tau)
     b.rho0 = float(box.rho0)
+    b.kT = float(getattr(box, "fluid_kT", 0.0))
     return b
 
 
@@ -202,11 +203,15 @@ def solid_mask(box) -> np.ndarray:
     return solid
 
 
-def lb_step(box, f: np.ndarray, S: Optional[np.ndarray] = None, work: Optional[np.ndarray] = None):
+def lb_step(box, f: np.ndarray, S: Optional[np.ndarray] = None, work: Optional[np.ndarray] = None,
+            step: int = 0, seed: int = 0):
+    """One LB step in place on f; the thermal source (box.fluid_kT > 0) draws its random
+    numbers for LB step `step` with key `seed`."""
     b = make_box(box)
     if work is None:
         work = np.empty_like(f)
-    bad = lib().ora_lb_step(C.byref(b), _dp(f), _dp(work), _dp(S) if S is not None else None)
+    bad = lib().ora_lb_step(C.byref(b), _dp(f), _dp(work), _dp(S) if S is not None else None,
+                            step & 0xFFFFFFFF, seed)
     return bad
 
 
@@ -347,7 +352,8 @@ class Sim:
                     _dp(self.v), _dp(self.u), _dp(self.fbar), _lp(self.node),
                     self.step_no & 0xFFFFFFFF, self.seed)
             else:
-                if L.ora_lb_step(C.byref(self._b), _dp(self.f), _dp(self.work), None) > 0:
+                if L.ora_lb_step(C.byref(self._b), _dp(self.f), _dp(self.work), None,
+                                 self.step_no & 0xFFFFFFFF, self.seed) > 0:
                     self.flags |= 16
             self.step_no += 1
             if self.n > 0 and self.t_done < 0:

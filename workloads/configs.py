@@ -36,6 +36,7 @@ class Box:
     walls: Tuple[Tuple[int, int, int, int, int, int], ...] = ()
     tau: float = 1.0
     rho0: float = 1.0
+    fluid_kT: float = 0.0  # temperature of the fluctuating-LB thermal source (0: none)
 
     @property
     def nodes(self) -> int:
