@@ -157,6 +157,18 @@ def extra_workloads(steps_scale=1.0):
     from workloads import configs as WC
 
     out = {}
+    # the paper's own polymer model (rigid bonds by SHAKE/RATTLE, M = 5) on 128x64x64 / N=100
+    w = WC.c2_paper_polymer(WC.STORE_F32)
+    log(f"workload {w.name} f32")
+    sim = build_case(w, WC.STORE_F32)
+    sim.step(50)
+    n = int(1000 * steps_scale)
+    dt = time_steps(sim, n)
+    md_avg, _ = event_time(sim.md_step, 50)
+    out[f"{w.name}:f32"] = {"mlups": round(w.fluid_nodes * n / dt / 1e6, 1), "ms_per_step": round(dt / n * 1e3, 5),
+                            "md_substeps": w.md.M, "bead_kernel_us": round(md_avg * 1e6, 2),
+                            "launch": sim.launch_shape()}
+    sim.close()
     base = None
     for st in (WC.STORE_F32, WC.STORE_F16, WC.STORE_BF16):
         w = WC.c3_translocation(st)

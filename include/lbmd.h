@@ -81,6 +81,8 @@ typedef struct lbmd_replica {
     lbmd_wall wall[LB_MAX_WALLS];
     double tau;            /* BGK relaxation time, > 1/2 (nu = (tau - 1/2)/3, Sec. II) */
     double rho0;           /* reference density; also the 16-bit deviation origin */
+    double fluid_kT;       /* temperature of the thermal source F_p of Eq. lbe (the
+                              fluctuating LB the paper cites; formula: lb_step); 0 = no F_p */
     int n_chains;          /* number of linear chains */
     const int* chain_len;  /* host, n_chains lengths >= 1; read during lb_init only */
     uint64_t seed;         /* Philox key (low word, high word) of this replica */
@@ -185,7 +187,15 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
 #define LB_STEP_NO_HYDRO 2u /* beads only, in a fluid at rest (the no-solvent comparison of
                                Sec. III): u_i = 0, no spreading, populations untouched */
 
-/* Enqueues n_steps LB time steps (Eq. lbe with Delta t = 1).  With
+/* Enqueues n_steps LB time steps (Eq. lbe with Delta t = 1).  The thermal source
+ * F_p (replicas with fluid_kT > 0; Sec. II gives no formula and cites the fluctuating LB
+ * of Adhikari et al.) is noise on the non-conserved moments of the collision with the
+ * covariance that keeps the equilibrium population fluctuations mu rho w_p at every
+ * node, mu = fluid_kT / c_s^2: F = phi Pi eta, phi = sqrt(mu rho (1 - (1 - omega)^2)),
+ * eta_p = sqrt(w_p) xi_p, (Pi x)_p = x_p - w_p (sum x + 3 c_p . sum c x), rho the
+ * pre-collision density; xi_p = sqrt(12) ((k_p + 1/2) / 2^24 - 1/2) with k_p the top 24
+ * bits of Philox4x32-10 word p of the counters (node, step, j, 2), j = 0..4, keyed by the
+ * replica seed (node = x + nx (y + ny z), step = the low word of the step counter).  With
  * LB_STEP_COUPLED each step is: nearest-node velocity interpolation at the beads,
  * M MD substeps with that velocity frozen, then the lattice update with the
  * spread reaction force S_p = -(w_p / c_s^2) Fbar_i . c_p added after collision

@@ -248,10 +248,50 @@ __device__ __forceinline__ typename Codec<S>::R collide(typename Codec<S>::R* f,
     return rho;
 }
 
+// Thermal source F_p of Eq. lbe (the fluctuating LB that Sec. II adopts), added to the
+// post-collision populations: F = phi Pi eta, eta_p = sqrt(w_p) xi_p with xi_p of zero
+// mean and unit variance (sqrt(12) times a symmetric uniform from Philox words p of the
+// counters (node, step, j, 2)), Pi x = x - w (sum x + 3 c . sum c x) (no density or
+// momentum in the noise), phi^2 = (kT / c_s^2) (1 - gamma^2) rho.  Its covariance
+// mu rho (1 - gamma^2) Pi W is what keeps the equilibrium fluctuations mu rho w_p of the
+// populations through a BGK collision with rate omega = 1 - gamma.
+template <class Rl>
+__device__ __forceinline__ void add_thermal(Rl* f, uint32_t node, uint32_t step, uint32_t k0, uint32_t k1,
+                                            Rl phi) {
+    Rl s0 = 0, sx = 0, sy = 0, sz = 0;
+    U4 w{0u, 0u, 0u, 0u};
+    for_pops([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        if constexpr (p % 4 == 0) w = philox4x32_10(U4{node, step, (uint32_t)(p / 4), 2u}, k0, k1);
+        uint32_t word;
+        if constexpr (p % 4 == 0) word = w.x;
+        else if constexpr (p % 4 == 1) word = w.y;
+        else if constexpr (p % 4 == 2) word = w.z;
+        else word = w.w;
+        // sqrt(12 w_p): 2 for the rest population, sqrt(2/3) and sqrt(1/3) for faces and edges
+        constexpr int c2 = cx_of(p) * cx_of(p) + cy_of(p) * cy_of(p) + cz_of(p) * cz_of(p);
+        constexpr double amp = c2 == 0 ? 2.0 : c2 == 1 ? 0.81649658092772603 : 0.57735026918962576;
+        const Rl eta = Rl(amp) * symmetric_uniform<Rl>(word);
+        s0 += eta;
+        if constexpr (cx_of(p) != 0) sx += Rl(cx_of(p)) * eta;
+        if constexpr (cy_of(p) != 0) sy += Rl(cy_of(p)) * eta;
+        if constexpr (cz_of(p) != 0) sz += Rl(cz_of(p)) * eta;
+        f[p] += phi * eta;
+    });
+    for_pops([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        Rl m = s0;
+        if constexpr (cx_of(p) != 0) m += Rl(3 * cx_of(p)) * sx;
+        if constexpr (cy_of(p) != 0) m += Rl(3 * cy_of(p)) * sy;
+        if constexpr (cz_of(p) != 0) m += Rl(3 * cz_of(p)) * sz;
+        f[p] -= phi * w_of<Rl>(p) * m;
+    });
+}
+
 // Thread-to-node mappings of the lattice kernel.
 enum LatticeMapping { MAP_FLAT = 0, MAP_ROWS = 1 };
 
-template <int S, int BLOCK, bool NT>
+template <int S, int BLOCK, bool NT, bool TH>
 __global__ __launch_bounds__(BLOCK) void k_stream_collide(const Replica* __restrict__ reps,
                                                           const int* __restrict__ prefix,
                                                           int n_reps,
@@ -318,6 +358,11 @@ __global__ __launch_bounds__(BLOCK) void k_stream_collide(const Replica* __restr
 
     const Rl rho = collide<S>(f, (Rl)R.omega, (Rl)R.rho0);
     if (!(rho > Rl(0)) || !(rho < Rl(1e30))) atomicOr(&st->err, LB_ERR_DENSITY);
+    if constexpr (TH) {
+        // the step counter does not move during a sweep with a thermal source
+        const Rl phi = sqrt(fmax((Rl)R.noise_c * rho, Rl(0)));
+        add_thermal<Rl>(f, (uint32_t)idx, (uint32_t)st->step, R.seed_lo, R.seed_hi, phi);
+    }
 
     typename C::T* __restrict__ out = dst + R.pop_base + idx;
     const long long V = R.V;
@@ -510,10 +555,10 @@ __global__ __launch_bounds__(256) void k_conserved_final(const double* __restric
 // ---------------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------------
-template <int S, int BLOCK, bool NT>
+template <int S, int BLOCK, bool NT, bool TH>
 static hipError_t launch_sc_n(const Context& c, const void* src, void* dst, bool bump, hipStream_t s) {
     using T = typename Codec<S>::T;
-    hipLaunchKernelGGL((k_stream_collide<S, BLOCK, NT>), dim3(c.lat.total_tiles), dim3(BLOCK), 0, s,
+    hipLaunchKernelGGL((k_stream_collide<S, BLOCK, NT, TH>), dim3(c.lat.total_tiles), dim3(BLOCK), 0, s,
                        c.d_reps, c.lat.d_prefix, (int)c.reps.size(), (const T*)src, (T*)dst, c.d_state,
                        bump ? 1 : 0, c.lat_chunk, c.lat.mapping);
     return hipGetLastError();
@@ -521,8 +566,14 @@ static hipError_t launch_sc_n(const Context& c, const void* src, void* dst, bool
 
 template <int S, int BLOCK>
 static hipError_t launch_sc_t(const Context& c, const void* src, void* dst, bool bump, hipStream_t s) {
-    return c.lat_nt ? launch_sc_n<S, BLOCK, true>(c, src, dst, bump, s)
-                    : launch_sc_n<S, BLOCK, false>(c, src, dst, bump, s);
+    if (c.thermal) {
+        // the thermal source reads the step counter, which must not move during the sweep
+        if (bump) return hipErrorInvalidValue;
+        return c.lat_nt ? launch_sc_n<S, BLOCK, true, true>(c, src, dst, false, s)
+                        : launch_sc_n<S, BLOCK, false, true>(c, src, dst, false, s);
+    }
+    return c.lat_nt ? launch_sc_n<S, BLOCK, true, false>(c, src, dst, bump, s)
+                    : launch_sc_n<S, BLOCK, false, false>(c, src, dst, bump, s);
 }
 
 template <int S>

@@ -169,6 +169,8 @@ int lb_validate_config(const lbmd_config* cfg) {
                 return fail(LB_EINVAL, at + "unknown boundary type");
         if (!(R.tau > 0.5) || !std::isfinite(R.tau)) return fail(LB_EINVAL, at + "tau must be > 1/2");
         if (!(R.rho0 > 0.0) || !std::isfinite(R.rho0)) return fail(LB_EINVAL, at + "rho0 must be > 0");
+        if (!(R.fluid_kT >= 0.0) || !std::isfinite(R.fluid_kT))
+            return fail(LB_EINVAL, at + "fluid_kT must be >= 0");
         if (R.n_walls < 0 || R.n_walls > LB_MAX_WALLS) return fail(LB_EINVAL, at + "n_walls out of range");
         for (int k = 0; k < R.n_walls; ++k) {
             const lbmd_wall& w = R.wall[k];
@@ -499,6 +501,12 @@ hipError_t enqueue_step(Context& c, int mode, int cur, hipStream_t main) {
         if ((e = hipStreamWaitEvent(main, c.ev_join, 0)) != hipSuccess) return e;
         return launch_spread(c, dst, true, main);
     }
+    // the thermal source reads the step counter in every block: it moves in a launch of
+    // its own after the sweep
+    if (c.thermal) {
+        hipError_t e = launch_stream_collide(c, src, dst, false, main);
+        return e != hipSuccess ? e : launch_bump(c, main);
+    }
     return launch_stream_collide(c, src, dst, true, main);
 }
 
@@ -593,6 +601,12 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
         R.seed_hi = (uint32_t)(in.seed >> 32);
         R.omega = 1.0 / in.tau;
         R.rho0 = in.rho0;
+        {
+            // thermal source amplitude: phi^2 / rho = (kT / c_s^2) (1 - gamma^2), gamma = 1 - omega
+            const double g = 1.0 - R.omega;
+            R.noise_c = 3.0 * in.fluid_kT * (1.0 - g * g);
+            if (in.fluid_kT > 0.0) c.thermal = true;
+        }
         R.xmid = in.n_walls > 0 ? 0.5 * (in.wall[0].x0 + in.wall[0].x1) : 0.5 * (in.nx - 1);
         R.div_nx = make_fastdiv((uint32_t)in.nx);
         R.div_ny = make_fastdiv((uint32_t)in.ny);

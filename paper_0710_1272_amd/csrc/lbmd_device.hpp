@@ -167,6 +167,7 @@ struct Replica {
     int bead0, n_beads;
     uint32_t seed_lo, seed_hi;
     double omega, rho0;
+    double noise_c;     // thermal source: phi^2 = noise_c rho (0 without one)
     double xmid;        // mid-plane of wall 0, for the translocation count
     FastDiv div_nx, div_ny;
 };
@@ -312,6 +313,12 @@ __host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
 template <class R>
 __host__ __device__ inline R centred_uniform(uint32_t r) {
     return (R)(int32_t)(r & 0xFFFFFF00u) * (R)(1.0 / 4294967296.0);
+}
+// top 24 bits k as (k + 1/2) / 2^24 - 1/2: symmetric about 0 in (-1/2, 1/2), variance
+// (1 - 2^-48) / 12; one rounding in FP32, exact in FP64
+template <class R>
+__host__ __device__ inline R symmetric_uniform(uint32_t r) {
+    return (R)(r >> 8) * (R)(1.0 / 16777216.0) + (R)(1.0 / 33554432.0 - 0.5);
 }
 
 // ---------------------------------------------------------------------------------

@@ -76,6 +76,7 @@ struct Context {
     LatticeLaunch lat;                 // current lattice launch shape
     int lat_chunk = -1;                // lattice tile order over XCDs (-1 contiguous, 0 none, C chunks)
     bool lat_nt = true;                // non-temporal population stores
+    bool thermal = false;              // some replica has a thermal source (fluid_kT > 0)
     std::vector<LatticeLaunch> lat_all;
     int md_lanes = 0;                  // lanes per bead of the bead kernel (0: by bead count)
 

@@ -45,7 +45,8 @@ class lbmd_wall(C.Structure):
 class lbmd_replica(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("bc", C.c_int * 3),
                 ("n_walls", C.c_int), ("wall", lbmd_wall * LB_MAX_WALLS), ("tau", C.c_double),
-                ("rho0", C.c_double), ("n_chains", C.c_int), ("chain_len", C.POINTER(C.c_int)),
+                ("rho0", C.c_double), ("fluid_kT", C.c_double), ("n_chains", C.c_int),
+                ("chain_len", C.POINTER(C.c_int)),
                 ("seed", C.c_uint64)]
 
 
@@ -149,6 +150,7 @@ class Config:
             for m, w in enumerate(box.walls):
                 R.wall[m] = lbmd_wall(*[int(t) for t in w])
             R.tau, R.rho0 = float(box.tau), float(box.rho0)
+            R.fluid_kT = float(getattr(box, "fluid_kT", 0.0))
             cl = np.ascontiguousarray(rep.chain_len, dtype=np.int32)
             self._keep.append(cl)
             R.n_chains = len(cl)

@@ -62,7 +62,7 @@ def _rep(**kw):
     dict(tau=0.5), dict(tau=float("nan")), dict(rho0=0.0), dict(nx=1),
     dict(walls=((1, 3, 7, 9, 7, 9),)), dict(walls=((14, 30, 7, 9, 7, 9),)),
     dict(walls=((14, 16, 7, 16, 7, 9),)), dict(walls=((14, 16, 7, 9, 7, 9), (17, 18, 7, 9, 7, 9))),
-    dict(bc=(2, 0, 0)),
+    dict(bc=(2, 0, 0)), dict(fluid_kT=-1e-4), dict(fluid_kT=float("inf")),
 ])
 def test_invalid_boxes_rejected(bad):
     c = _cfg([_rep(**bad)])
