@@ -445,8 +445,9 @@ __device__ __forceinline__ int build_list(int i, int n, bool bn, bool bp, const 
 // (then G = 1).  WCA pairs come from a Verlet list (radius rc + skin), kept across LB
 // steps and rebuilt whenever a bead has moved skin/2 since the last build, so the set
 // of interacting pairs is exactly that of the all-pairs definition.
-// Positions are double-buffered in LDS: one barrier per substep.
-template <class Real, int G, int BPT, bool PERIODIC, int MAXT>
+// Positions are double-buffered in LDS: one barrier per substep.  POLY compiles in the
+// angular term and rigid bonds (the kernel without them is the harmonic-chain model).
+template <class Real, int G, int BPT, bool PERIODIC, int MAXT, bool POLY>
 __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
     extern __shared__ double lds[];
     __shared__ double red[16 * 4];
@@ -667,8 +668,8 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
         bpp[k] = bpk[k] && i > 1 && BN[i - 2] != 0;
     }
     // rigid chains (at most 512 beads, one bond row per thread) only run with one bead per group
-    const bool rigid = BPT == 1 && md.rigid != 0;
-    const Real kappa = (Real)md.kappa_phi;
+    const bool rigid = POLY && BPT == 1 && md.rigid != 0;
+    const Real kappa = POLY ? (Real)md.kappa_phi : Real(0);
     constexpr int K = SlotsPerLane<G, BPT, MAXT>::K;
     int slot[BPT][K], nslot[BPT];
     // Beads within reach of a wall slab or a free-slip face.  Decided at each list build
@@ -809,7 +810,7 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
                 for (int c = 0; c < 3; ++c) F[k][c] += coef * d[c];
             }
             // angular terms centred on i - 1, i and i + 1 (each needs both of its bonds)
-            if (kappa != Real(0) && (bpk[k] || bnk[k])) {
+            if (POLY && kappa != Real(0) && (bpk[k] || bnk[k])) {
                 const int jmm = bpp[k] ? i - 2 : i, jpp = bnn[k] ? i + 2 : i;
                 const double pmm[3] = {PX[jmm], PY[jmm], PZ[jmm]};
                 const double ppp[3] = {PX[jpp], PY[jpp], PZ[jpp]};
@@ -908,7 +909,7 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
                 for (int c = 0; c < 3; ++c) QX[c * nmax + i] = r[k][c];
             }
         }
-        if (rigid) {
+        if (POLY && rigid) {
             // SHAKE and RATTLE on the unconstrained positions now in QX (PX still holds
             // the positions of the start of the substep); row t of the bond systems is
             // thread t, bond t joining beads t and t + 1
@@ -1255,7 +1256,7 @@ bool md_lanes_valid(int lanes, int max_beads) {
     return (lanes == 2 || lanes == 4 || lanes == 8 || lanes == 16) && (long long)lanes * max_beads <= 512;
 }
 
-template <class Real, int G, int BPT, bool PER, int MAXT>
+template <class Real, int G, int BPT, bool PER, int MAXT, bool POLY>
 static hipError_t launch_md_t(const Context& c, const void* cur, int mode, int block, hipStream_t s) {
     MDKArgs<Real> a;
     a.reps = c.d_reps;
@@ -1270,17 +1271,17 @@ static hipError_t launch_md_t(const Context& c, const void* cur, int mode, int b
     const size_t lds = md_lds_bytes(c, G);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_md<Real, G, BPT, PER, MAXT>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_md<Real, G, BPT, PER, MAXT, POLY>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_md<Real, G, BPT, PER, MAXT>), dim3((unsigned)c.reps.size()), dim3(block), lds, s, a,
+    hipLaunchKernelGGL((k_md<Real, G, BPT, PER, MAXT, POLY>), dim3((unsigned)c.reps.size()), dim3(block), lds, s, a,
                        c.storage);
     return hipGetLastError();
 }
 
-template <class Real, bool PER>
+template <class Real, bool PER, bool POLY>
 static hipError_t launch_md_g(const Context& c, const void* cur, int mode, hipStream_t s) {
     // G lanes per bead (the context's choice); with one lane per bead the 512-thread
     // bound up to 512 beads, the 1024-thread bound beyond, up to 4 beads per lane
@@ -1289,17 +1290,17 @@ static hipError_t launch_md_g(const Context& c, const void* cur, int mode, hipSt
     if (!md_lanes_valid(G, m)) return hipErrorInvalidValue;
     auto blk = [](int t) { return std::min(1024, (t + 63) / 64 * 64); };
     switch (G) {
-        case 16: return launch_md_t<Real, 16, 1, PER, 512>(c, cur, mode, blk(16 * m), s);
-        case 8: return launch_md_t<Real, 8, 1, PER, 512>(c, cur, mode, blk(8 * m), s);
-        case 4: return launch_md_t<Real, 4, 1, PER, 512>(c, cur, mode, blk(4 * m), s);
-        case 2: return launch_md_t<Real, 2, 1, PER, 512>(c, cur, mode, blk(2 * m), s);
+        case 16: return launch_md_t<Real, 16, 1, PER, 512, POLY>(c, cur, mode, blk(16 * m), s);
+        case 8: return launch_md_t<Real, 8, 1, PER, 512, POLY>(c, cur, mode, blk(8 * m), s);
+        case 4: return launch_md_t<Real, 4, 1, PER, 512, POLY>(c, cur, mode, blk(4 * m), s);
+        case 2: return launch_md_t<Real, 2, 1, PER, 512, POLY>(c, cur, mode, blk(2 * m), s);
         default: break;
     }
-    if (m <= 512) return launch_md_t<Real, 1, 1, PER, 512>(c, cur, mode, blk(m), s);
-    if (m <= 1024) return launch_md_t<Real, 1, 1, PER, 1024>(c, cur, mode, blk(m), s);
-    if (m <= 2048) return launch_md_t<Real, 1, 2, PER, 1024>(c, cur, mode, 1024, s);
-    if (m <= 3072) return launch_md_t<Real, 1, 3, PER, 1024>(c, cur, mode, 1024, s);
-    if (m <= 4096) return launch_md_t<Real, 1, 4, PER, 1024>(c, cur, mode, 1024, s);
+    if (m <= 512) return launch_md_t<Real, 1, 1, PER, 512, POLY>(c, cur, mode, blk(m), s);
+    if (m <= 1024) return launch_md_t<Real, 1, 1, PER, 1024, POLY>(c, cur, mode, blk(m), s);
+    if (m <= 2048) return launch_md_t<Real, 1, 2, PER, 1024, POLY>(c, cur, mode, 1024, s);
+    if (m <= 3072) return launch_md_t<Real, 1, 3, PER, 1024, POLY>(c, cur, mode, 1024, s);
+    if (m <= 4096) return launch_md_t<Real, 1, 4, PER, 1024, POLY>(c, cur, mode, 1024, s);
     return hipErrorInvalidValue;
 }
 
@@ -1308,7 +1309,11 @@ static hipError_t launch_md_r(const Context& c, const void* cur, int mode, hipSt
     bool any_periodic = false;
     for (const Replica& R : c.reps)
         if (R.n_beads > 0 && (!R.fs[0] || !R.fs[1] || !R.fs[2])) any_periodic = true;
-    return any_periodic ? launch_md_g<Real, true>(c, cur, mode, s) : launch_md_g<Real, false>(c, cur, mode, s);
+    if (c.md.rigid || c.md.kappa_phi != 0.0)
+        return any_periodic ? launch_md_g<Real, true, true>(c, cur, mode, s)
+                            : launch_md_g<Real, false, true>(c, cur, mode, s);
+    return any_periodic ? launch_md_g<Real, true, false>(c, cur, mode, s)
+                        : launch_md_g<Real, false, false>(c, cur, mode, s);
 }
 
 hipError_t launch_md(const Context& c, const void* cur, int mode, hipStream_t s) {
