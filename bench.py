@@ -169,6 +169,23 @@ def extra_workloads(steps_scale=1.0):
                             "md_substeps": w.md.M, "bead_kernel_us": round(md_avg * 1e6, 2),
                             "launch": sim.launch_shape()}
     sim.close()
+    # the fluctuating lattice (thermal source F_p at kT = 1e-4) on the same 128x64x64 / N=100 set-up
+    import dataclasses
+    w = WC.c2_translocation(WC.STORE_F32)
+    rep = w.replicas[0]
+    w = dataclasses.replace(w, name=w.name + "_thermal",
+                            replicas=[dataclasses.replace(rep, box=dataclasses.replace(rep.box, fluid_kT=1e-4))])
+    log(f"workload {w.name} f32")
+    sim = build_case(w, WC.STORE_F32)
+    sim.step(50)
+    n = int(2000 * steps_scale)
+    dt = time_steps(sim, n)
+    rl = lattice_roofline(sim, w.fluid_nodes, WC.STORE_F32, n=96)
+    out[f"{w.name}:f32"] = {"mlups": round(w.fluid_nodes * n / dt / 1e6, 1), "ms_per_step": round(dt / n * 1e3, 5),
+                            "fluid_kT": 1e-4, "lattice_only_step": rl, "launch": sim.launch_shape(),
+                            "note": "lattice-only steps with a thermal source are two launches (the sweep, "
+                                    "then the step-counter increment)"}
+    sim.close()
     base = None
     for st in (WC.STORE_F32, WC.STORE_F16, WC.STORE_BF16):
         w = WC.c3_translocation(st)
