@@ -138,6 +138,10 @@ typedef struct lbmd_config {
                                           1, or 2/4/8/16 with lanes x (beads of the largest
                                           replica) <= 512; LB_CFG_AUTOTUNE times the choices */
     unsigned flags;                    /* LB_CFG_* */
+    int obs_every;                     /* record the translocation observables (LB_MOM_OBSERVABLES)
+                                          after every step whose new step count is a multiple of
+                                          obs_every; 0 = none */
+    int obs_capacity;                  /* rows kept per replica (later rows are counted, not kept) */
 } lbmd_config;
 
 /* lattice_mapping */
@@ -227,6 +231,15 @@ int md_step(lbmd_ctx* ctx);
 #define LB_MOM_TRANSLOC 5u    /* 6 doubles: N_T, completion step (-1 if none), COM x, y, z, step */
 #define LB_MOM_COUPLING 6u    /* [n][3] u_i, [n][3] Fbar_i, [n] node index (-1 on solid), doubles */
 #define LB_MOM_STATUS 7u      /* 2 doubles: device error word, LB step counter */
+#define LB_MOM_OBSERVABLES 8u /* [1 + obs_capacity][8] doubles: row 0 = (rows recorded, obs_every,
+                                 obs_capacity, 0...); then one row per recorded bead step:
+                                 step count after it, N_T, S_H, S_E, K, R_U^2, R_T^2, x of the centre of
+                                 mass (the Sec. III analysis: S_H = m gamma sum v_i . u_i (eq. Shydro)
+                                 with u_i the fluid velocity interpolated for that step, S_E = sum
+                                 F_drive,i . v_i (eq. Selec) over beads whose nearest node is a pore
+                                 node, K = m/2 sum |v_i|^2, R_U^2 / R_T^2 the squared radii of
+                                 gyration of the beads at x <= / > the mid-plane of wall 0, 0 for an
+                                 empty part); recorded in coupled, no-solvent and md_step bead steps */
 
 /* Observables of one replica (Sec. II Eqs. dens and vel; Sec. III translocation
  * coordinate).  Synchronises the stream and copies into host_out (bytes long).

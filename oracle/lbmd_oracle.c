@@ -917,6 +917,59 @@ int ora_transloc(const ora_box* b, int n, const double* r, double* com)
     return nt;
 }
 
+/* Observables of the translocation analysis (Sec. III) for the state at the end of an LB
+ * step; u holds the fluid velocity interpolated at each bead for that step (0 without a
+ * solvent).  out[0] N_T (beads past the mid-plane of wall 0); out[1] S_H = m gamma sum_i
+ * v_i . u_i, the work rate of the fluid on the chain (eq. Shydro; the drag's fluid part
+ * m gamma u_i times v_i); out[2] S_E = sum_i F_drive,i . v_i (eq. Selec; the drive acts on
+ * beads whose nearest node is a pore node); out[3] K = m/2 sum_i |v_i|^2; out[4], out[5] the
+ * squared radii of gyration of the untranslocated (x <= mid-plane) and translocated beads,
+ * sum |r_i - r_c|^2 / n over each part (0 for an empty part); out[6] x of the centre of
+ * mass. */
+void ora_observables(const ora_box* b, const ora_md* md, int n, const double* r, const double* v,
+                     const double* u, double* out)
+{
+    const double xmid = b->n_walls > 0 ? 0.5 * (b->wall[0][0] + b->wall[0][1]) : 0.5 * (b->nx - 1);
+    double com[3];
+    int nt = ora_transloc(b, n, r, com);
+    double sh = 0.0, se = 0.0, ke = 0.0;
+    for (int i = 0; i < n; ++i) {
+        int g[3];
+        ngp(b, r + 3 * i, g);
+        for (int a = 0; a < 3; ++a) {
+            sh += v[3 * i + a] * u[3 * i + a];
+            ke += v[3 * i + a] * v[3 * i + a];
+        }
+        if (ora_is_pore(b, g[0], g[1], g[2])) se += md->drive_sign * md->f_drive * v[3 * i];
+    }
+    /* radii of gyration: centre of each part first, then the mean squared distance */
+    double rg2[2] = {0.0, 0.0};
+    for (int part = 0; part < 2; ++part) {
+        double c[3] = {0.0, 0.0, 0.0};
+        int cnt = 0;
+        for (int i = 0; i < n; ++i) {
+            if ((r[3 * i] > xmid) != (part == 1)) continue;
+            for (int a = 0; a < 3; ++a) c[a] += r[3 * i + a];
+            ++cnt;
+        }
+        if (cnt == 0) continue;
+        for (int a = 0; a < 3; ++a) c[a] /= cnt;
+        double s2 = 0.0;
+        for (int i = 0; i < n; ++i) {
+            if ((r[3 * i] > xmid) != (part == 1)) continue;
+            for (int a = 0; a < 3; ++a) s2 += (r[3 * i + a] - c[a]) * (r[3 * i + a] - c[a]);
+        }
+        rg2[part] = s2 / cnt;
+    }
+    out[0] = nt;
+    out[1] = md->mass * md->gamma * sh;
+    out[2] = se;
+    out[3] = 0.5 * md->mass * ke;
+    out[4] = rg2[0];
+    out[5] = rg2[1];
+    out[6] = com[0];
+}
+
 /* One coupled LB time step in the order of Sec. II:
  *   1. interpolate u(x) -> u_i at the beads' nodes;
  *   2. M MD substeps with u_i frozen;

@@ -85,6 +85,7 @@ def lib():
         L.ora_shake_rattle.argtypes = [bp, mp, C.c_int, C.c_int, ip, dp, dp, dp, C.c_double]
         L.ora_coupled_step.argtypes = [bp, mp, C.c_int, C.c_int, ip, dp, dp, dp, dp, dp, dp, dp,
                                        lp, C.c_uint32, C.c_uint64]
+        L.ora_observables.argtypes = [bp, mp, C.c_int, dp, dp, dp, dp]
         L.ora_lattice.argtypes = [ip, dp, ip]
         L.ora_cs2.restype = C.c_double
         L.ora_threads.restype = C.c_int
@@ -308,6 +309,22 @@ def transloc(box, r: np.ndarray):
     return nt, com
 
 
+OBSERVABLES = ("N_T", "S_H", "S_E", "K", "R_U2", "R_T2", "x_com")
+
+
+def observables(box, md, r: np.ndarray, v: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """The translocation observables of Sec. III for one state (names in OBSERVABLES):
+    N_T, S_H = m gamma sum v.u, S_E = sum F_drive.v, K, squared radii of gyration of the
+    untranslocated and translocated parts, x of the centre of mass."""
+    out = np.zeros(7)
+    n = len(r)
+    lib().ora_observables(C.byref(make_box(box)), C.byref(make_md(md)), n,
+                          _dp(np.ascontiguousarray(r, dtype=np.float64)),
+                          _dp(np.ascontiguousarray(v, dtype=np.float64)),
+                          _dp(np.ascontiguousarray(u, dtype=np.float64)), _dp(out))
+    return out
+
+
 class Sim:
     """One replica advanced by the oracle: populations, beads, step counter."""
 
@@ -334,6 +351,11 @@ class Sim:
     def n(self) -> int:
         return len(self.r)
 
+    def observables(self) -> np.ndarray:
+        """Translocation observables of the current state with this step's interpolated
+        fluid velocity (zero after lattice-only or no-solvent steps)."""
+        return observables(self.box, self.md, self.r, self.v, self.u)
+
     def step(self, n_steps: int = 1, coupled: bool = True, hydro: bool = True):
         """n LB steps: coupled (Sec. II), lattice only, or, with hydro=False, the beads
         alone in a fluid at rest (u = 0; the no-solvent comparison of Sec. III): the
@@ -342,8 +364,10 @@ class Sim:
         for _ in range(n_steps):
             if not hydro:
                 if self.n > 0:
-                    _, fl = md_substeps(self.box, self.md, self.chain_len, self.r, self.v,
-                                        np.zeros((self.n, 3)), self.step_no, self.seed)
+                    self.u[:] = 0.0
+                    fbar, fl = md_substeps(self.box, self.md, self.chain_len, self.r, self.v,
+                                           self.u, self.step_no, self.seed)
+                    self.fbar[:] = fbar
                     self.flags |= fl
             elif coupled and self.n > 0:
                 self.flags |= L.ora_coupled_step(

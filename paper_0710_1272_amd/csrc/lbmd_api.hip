@@ -102,7 +102,7 @@ WorkLayout work_layout(int n_reps, int max_V, long long max_stage_nodes) {
     return L;
 }
 
-BeadLayout bead_layout(int ntot, int n_reps, size_t rs) {
+BeadLayout bead_layout(int ntot, int n_reps, size_t rs, int obs_rows) {
     BeadLayout L{};
     size_t off = 0;
     const size_t N = (size_t)std::max(ntot, 1);
@@ -119,6 +119,7 @@ BeadLayout bead_layout(int ntot, int n_reps, size_t rs) {
     L.nlist = off;    off += align256((size_t)kNeighbourMax * N * sizeof(unsigned short));
     L.ncount = off;   off += align256(N * sizeof(int));
     L.rref = off;     off += align256(3 * N * sizeof(double));
+    L.obs = off;      off += align256((size_t)std::max(n_reps, 1) * (size_t)obs_rows * 8 * sizeof(double));
     L.total = off;
     return L;
 }
@@ -194,6 +195,8 @@ int lb_validate_config(const lbmd_config* cfg) {
         total_beads += nb;
         max_beads = std::max(max_beads, nb);
     }
+    if (cfg->obs_every < 0 || (cfg->obs_every > 0 && (cfg->obs_capacity < 1 || cfg->obs_capacity > (1 << 24))))
+        return fail(LB_EINVAL, "obs_every must be >= 0, and obs_capacity in 1..2^24 when recording");
     if (cfg->md_lanes != 0 && !md_lanes_valid(cfg->md_lanes, max_beads))
         return fail(LB_EINVAL, "md_lanes must be 0, 1, or 2/4/8/16 with md_lanes x beads per replica <= 512");
     const lbmd_md_params& m = cfg->md;
@@ -219,12 +222,15 @@ int lb_validate_config(const lbmd_config* cfg) {
     return LB_OK;
 }
 
+static int obs_rows(const lbmd_config* cfg) { return cfg->obs_every > 0 ? cfg->obs_capacity + 1 : 0; }
+
 size_t lb_required_bytes(const lbmd_config* cfg, int which) {
     if (lb_validate_config(cfg) != LB_OK) return 0;
     const Totals t = totals(cfg);
     switch (which) {
         case LB_BUF_POPS: return align256((size_t)19 * (size_t)t.nodes * store_size(cfg->storage));
-        case LB_BUF_BEADS: return bead_layout(t.beads, cfg->n_replicas, real_size(cfg->storage)).total;
+        case LB_BUF_BEADS:
+            return bead_layout(t.beads, cfg->n_replicas, real_size(cfg->storage), obs_rows(cfg)).total;
         case LB_BUF_WORK: return work_layout(cfg->n_replicas, t.max_V, kStageNodes).total;
         default: g_last_error = "unknown buffer id"; return 0;
     }
@@ -246,7 +252,8 @@ int set_lattice_shape(Context& c, int block, int mapping = -1) {
 
 template <class Real>
 int setup_beads(Context& c, const lbmd_config* cfg) {
-    const BeadLayout L = bead_layout(c.ntot_beads, (int)c.reps.size(), sizeof(Real));
+    const BeadLayout L = bead_layout(c.ntot_beads, (int)c.reps.size(), sizeof(Real),
+                                     c.obs_every > 0 ? c.obs_capacity + 1 : 0);
     char* base = (char*)c.beads;
     BeadPtrs<Real>* p = new (std::nothrow) BeadPtrs<Real>;
     if (!p) return fail(LB_ENOMEM, "host allocation");
@@ -263,6 +270,9 @@ int setup_beads(Context& c, const lbmd_config* cfg) {
     p->nlist = (unsigned short*)(base + L.nlist);
     p->ncount = (int*)(base + L.ncount);
     p->rref = (double*)(base + L.rref);
+    p->obs = (double*)(base + L.obs);
+    p->obs_every = c.obs_every;
+    p->obs_cap = c.obs_capacity;
     p->ntot = c.ntot_beads;
     c.bead_ptrs = p;
 
@@ -305,6 +315,18 @@ int setup_beads(Context& c, const lbmd_config* cfg) {
         HIP_TRY(hipMemcpy(p->rep_of, rep_of.data(), N * sizeof(int), hipMemcpyHostToDevice));
     }
     HIP_TRY(hipMemcpy(p->diag, diag.data(), 8 * c.reps.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (c.obs_every > 0) {
+        // header rows (rows recorded, every, capacity); the rows themselves start unset (step -1)
+        const size_t rows = (size_t)c.obs_capacity + 1;
+        std::vector<double> rec(c.reps.size() * rows * 8, 0.0);
+        for (size_t r = 0; r < c.reps.size(); ++r) {
+            double* h = rec.data() + r * rows * 8;
+            h[1] = c.obs_every;
+            h[2] = c.obs_capacity;
+            for (size_t k = 1; k < rows; ++k) h[k * 8] = -1.0;
+        }
+        HIP_TRY(hipMemcpy(p->obs, rec.data(), rec.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     return LB_OK;
 }
 
@@ -396,7 +418,8 @@ int autotune_md(Context& c) {
         if (md_lanes_valid(G, c.max_beads)) cand.push_back(G);
     if (cand.size() < 2) return LB_OK;
     const size_t real = c.storage == LB_STORE_F64 ? sizeof(double) : sizeof(float);
-    const size_t bytes = bead_layout(c.ntot_beads, (int)c.reps.size(), real).total;
+    const size_t bytes =
+        bead_layout(c.ntot_beads, (int)c.reps.size(), real, c.obs_every > 0 ? c.obs_capacity + 1 : 0).total;
     void* save = nullptr;
     HIP_TRY(hipMalloc(&save, bytes + sizeof(RunState)));
     RunState* save_st = (RunState*)((char*)save + bytes);
@@ -568,6 +591,8 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
     c.max_beads = t.max_beads;
     c.max_V = t.max_V;
     c.md_lanes = cfg->md_lanes;
+    c.obs_every = cfg->obs_every;
+    c.obs_capacity = cfg->obs_every > 0 ? cfg->obs_capacity : 0;
 
     // replica descriptors
     long long pop_base = 0;
@@ -824,6 +849,8 @@ size_t lb_moments_bytes(const lbmd_ctx* ctx, int replica, unsigned what) {
         case LB_MOM_TRANSLOC: return 6 * sizeof(double);
         case LB_MOM_COUPLING: return 7 * n * sizeof(double);
         case LB_MOM_STATUS: return 2 * sizeof(double);
+        case LB_MOM_OBSERVABLES:
+            return ctx->c.obs_every > 0 ? ((size_t)ctx->c.obs_capacity + 1) * 8 * sizeof(double) : 0;
         default: return 0;
     }
 }
@@ -936,6 +963,14 @@ int lb_moments(lbmd_ctx* ctx, int replica, unsigned what, void* host_out, size_t
         }
         case LB_MOM_STATUS:
             break;
+        case LB_MOM_OBSERVABLES: {
+            const double* obs = c.storage == LB_STORE_F64 ? ((BeadPtrs<double>*)c.bead_ptrs)->obs
+                                                          : ((BeadPtrs<float>*)c.bead_ptrs)->obs;
+            const size_t rows = (size_t)c.obs_capacity + 1;
+            HIP_TRY(hipMemcpyAsync(out, obs + (size_t)replica * rows * 8, rows * 8 * sizeof(double),
+                                   hipMemcpyDeviceToHost, c.stream));
+            break;
+        }
     }
     HIP_TRY(hipMemcpyAsync(hst, c.d_state, sizeof(RunState), hipMemcpyDeviceToHost, c.stream));
     HIP_TRY(hipStreamSynchronize(c.stream));

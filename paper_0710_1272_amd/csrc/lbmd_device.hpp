@@ -350,6 +350,8 @@ struct BeadPtrs {
     int* ncount;        // [Ntot] number of neighbours; > kNeighbourMax means overflow
     double* rref;       // [3][Ntot] positions at the last list build (lists are kept across
                         // LB steps while diag[7] of the replica is 1)
+    double* obs;        // [n_replicas][obs_cap + 1][8] observable record (header row first)
+    int obs_every, obs_cap;
     int ntot;
 };
 

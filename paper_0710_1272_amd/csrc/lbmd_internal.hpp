@@ -77,6 +77,7 @@ struct Context {
     int lat_chunk = -1;                // lattice tile order over XCDs (-1 contiguous, 0 none, C chunks)
     bool lat_nt = true;                // non-temporal population stores
     bool thermal = false;              // some replica has a thermal source (fluid_kT > 0)
+    int obs_every = 0, obs_capacity = 0;  // observable record (0: none)
     std::vector<LatticeLaunch> lat_all;
     int md_lanes = 0;                  // lanes per bead of the bead kernel (0: by bead count)
 
@@ -97,9 +98,10 @@ WorkLayout work_layout(int n_reps, int max_V, long long max_stage_nodes);
 
 // bead-buffer layout
 struct BeadLayout {
-    size_t r, v, u, fbar, node, bond_next, agg_at, agg_f, rep_of, diag, nlist, ncount, rref, total;
+    size_t r, v, u, fbar, node, bond_next, agg_at, agg_f, rep_of, diag, nlist, ncount, rref, obs, total;
 };
-BeadLayout bead_layout(int ntot, int n_reps, size_t real_size);
+// obs_rows: rows of the observable record per replica (capacity + 1 header row; 0 = none)
+BeadLayout bead_layout(int ntot, int n_reps, size_t real_size, int obs_rows);
 
 // kernel launchers (lb_kernels.hip / md_kernels.hip); all enqueue on `s`
 hipError_t launch_stream_collide(const Context& c, const void* src, void* dst, bool bump_step,

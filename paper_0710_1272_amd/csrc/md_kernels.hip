@@ -450,7 +450,7 @@ __device__ __forceinline__ int build_list(int i, int n, bool bn, bool bp, const 
 template <class Real, int G, int BPT, bool PERIODIC, int MAXT, bool POLY>
 __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
     extern __shared__ double lds[];
-    __shared__ double red[16 * 4];
+    __shared__ double red[16 * 8];
     const int NG = blockDim.x / G;  // groups per block
     const Replica& R = a.reps[blockIdx.x];
     const Geom GM = load_geom(R);
@@ -1104,6 +1104,72 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
     }
     block_sums<Real>(acc, 4, red);
 
+    // observable record of the translocation analysis (Sec. III), one row every obs_every
+    // steps: work rates S_H = m gamma sum v.u and S_E = sum F_drive.v, kinetic energy, and
+    // the radii of gyration of the two sides of the wall from FP64 sums of positions taken
+    // relative to the pore centre (which keeps the second moments small)
+    if (a.b.obs_every > 0 && (a.mode & MD_SUBSTEPS) && (step + 1) % a.b.obs_every == 0) {
+        const double ref[3] = {xmid, 0.5 * nd[1], 0.5 * nd[2]};
+        double o[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // S_H, S_E, K, sum d^2, trans: sum d (3), sum d^2
+#pragma unroll
+        for (int k = 0; k < BPT; ++k) {
+            if (!own[k] || gl != 0) continue;
+            double vu = 0.0, vv = 0.0, d2 = 0.0, dd[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                vu += (double)v[k][c] * (double)u[k][c];
+                vv += (double)v[k][c] * (double)v[k][c];
+                dd[c] = r[k][c] - ref[c];
+                d2 += dd[c] * dd[c];
+            }
+            bool pore = false;
+#pragma unroll
+            for (int w = 0; w < LB_MAX_WALLS; ++w) {
+                if (w >= GM.n_walls) break;
+                pore = pore || wall_pore_node<PERIODIC>(GM, GM.wall[w], r[k]);
+            }
+            o[0] += md.mass * md.gamma * vu;
+            o[1] += pore ? md.f_drive * (double)v[k][0] : 0.0;
+            o[2] += 0.5 * md.mass * vv;
+            o[3] += d2;
+            if (r[k][0] > xmid) {
+                o[4] += dd[0];
+                o[5] += dd[1];
+                o[6] += dd[2];
+                o[7] += d2;
+            }
+        }
+        block_sums<Real>(o, 8, red);
+        if (tid == 0) {
+            double* rec = a.b.obs + (size_t)blockIdx.x * ((size_t)a.b.obs_cap + 1) * 8;
+            const double cnt = rec[0];
+            if (cnt < (double)a.b.obs_cap) {
+                const double nT = acc[0], nU = (double)n - acc[0];
+                // all-bead sums of d = r - ref from the position sums
+                const double sa[3] = {acc[1] - n * ref[0], acc[2] - n * ref[1], acc[3] - n * ref[2]};
+                double rT = 0.0, rU = 0.0;
+                if (nT > 0) {
+                    const double c0 = o[4] / nT, c1 = o[5] / nT, c2 = o[6] / nT;
+                    rT = fmax(o[7] / nT - (c0 * c0 + c1 * c1 + c2 * c2), 0.0);
+                }
+                if (nU > 0) {
+                    const double c0 = (sa[0] - o[4]) / nU, c1 = (sa[1] - o[5]) / nU, c2 = (sa[2] - o[6]) / nU;
+                    rU = fmax((o[3] - o[7]) / nU - (c0 * c0 + c1 * c1 + c2 * c2), 0.0);
+                }
+                double* row = rec + (size_t)(1 + (long long)cnt) * 8;
+                row[0] = (double)(step + 1);
+                row[1] = nT;
+                row[2] = o[0];
+                row[3] = o[1];
+                row[4] = o[2];
+                row[5] = rU;
+                row[6] = rT;
+                row[7] = acc[1] / n;
+            }
+            rec[0] = cnt + 1.0;
+        }
+    }
+
     // one leader per occupied node (its lowest-index bead) sums the Fbar of the beads on
     // it in index order; a bead alone on its node is its own sum
     double* FX = P;  // positions are no longer needed
@@ -1208,6 +1274,8 @@ __global__ void k_bump(RunState* st) { st->step += 1; }
 static int md_nmax(const Context& c) { return (c.max_beads + 63) / 64 * 64; }
 
 static constexpr size_t kMDLdsBudget = 150 * 1024;
+// the bead kernel's static LDS (block sums 1 KB, rebuild vote 32 B) stays below this
+static constexpr int kMDStaticLds = 2048;
 
 static size_t md_base_lds(size_t nmax) { return nmax * (6 * sizeof(double) + sizeof(int) + 1); }
 // SHAKE/RATTLE work area of rigid chains: 15 doubles per bead, always in LDS
@@ -1272,7 +1340,8 @@ static hipError_t launch_md_t(const Context& c, const void* cur, int mode, int b
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)k_md<Real, G, BPT, PER, MAXT, POLY>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024 - kMDStaticLds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }

@@ -27,7 +27,9 @@ LB_BUF_POPS, LB_BUF_BEADS, LB_BUF_WORK = 0, 1, 2
 LB_STEP_COUPLED, LB_STEP_NO_HYDRO = 1, 2
 LB_COUPLE_INTERP, LB_COUPLE_SPREAD = 1, 2
 (LB_MOM_CONSERVED, LB_MOM_FIELDS, LB_MOM_POPULATIONS, LB_MOM_BEADS, LB_MOM_TRANSLOC,
- LB_MOM_COUPLING, LB_MOM_STATUS) = 1, 2, 3, 4, 5, 6, 7
+ LB_MOM_COUPLING, LB_MOM_STATUS, LB_MOM_OBSERVABLES) = 1, 2, 3, 4, 5, 6, 7, 8
+# columns of an LB_MOM_OBSERVABLES row
+OBS_COLUMNS = ("step", "N_T", "S_H", "S_E", "K", "R_U2", "R_T2", "x_com")
 LB_ERR_BEAD_IN_SOLID, LB_ERR_BEAD_OUTSIDE, LB_ERR_NONFINITE, LB_ERR_BOND_STRETCH, LB_ERR_DENSITY = (
     1, 2, 4, 8, 16)
 LB_ERR_CONSTRAINT = 32
@@ -68,7 +70,8 @@ class lbmd_config(C.Structure):
     _fields_ = [("n_replicas", C.c_int), ("replicas", C.POINTER(lbmd_replica)), ("storage", C.c_int),
                 ("md", lbmd_md_params), ("init", C.POINTER(lbmd_initial_state)),
                 ("block_size", C.c_int), ("lattice_mapping", C.c_int), ("xcd_order", C.c_int),
-                ("md_lanes", C.c_int), ("flags", C.c_uint)]
+                ("md_lanes", C.c_int), ("flags", C.c_uint), ("obs_every", C.c_int),
+                ("obs_capacity", C.c_int)]
 
 
 class lbmd_buffers(C.Structure):
@@ -136,7 +139,8 @@ class Config:
 
     def __init__(self, replicas, md, storage: int, init: Optional[dict] = None,
                  block_size: int = 0, flags: int = 0, mapping: int = LB_MAP_AUTO,
-                 xcd_order: int = LB_XCD_AUTO, md_lanes: int = 0):
+                 xcd_order: int = LB_XCD_AUTO, md_lanes: int = 0, obs_every: int = 0,
+                 obs_capacity: int = 0):
         self._keep: List[object] = []
         n = len(replicas)
         self.reps = (lbmd_replica * n)()
@@ -179,6 +183,8 @@ class Config:
         self.cfg.xcd_order = int(xcd_order)
         self.cfg.md_lanes = int(md_lanes)
         self.cfg.flags = int(flags)
+        self.cfg.obs_every = int(obs_every)
+        self.cfg.obs_capacity = int(obs_capacity)
 
     def validate(self) -> int:
         return lib().lb_validate_config(C.byref(self.cfg))
@@ -192,14 +198,16 @@ class Simulation:
 
     def __init__(self, replicas, md, storage: int, init: Optional[dict] = None,
                  block_size: int = 0, flags: int = 0, device_buffers: bool = True,
-                 mapping: int = LB_MAP_AUTO, xcd_order: int = LB_XCD_AUTO, md_lanes: int = 0):
+                 mapping: int = LB_MAP_AUTO, xcd_order: int = LB_XCD_AUTO, md_lanes: int = 0,
+                 obs_every: int = 0, obs_capacity: int = 0):
         import torch
 
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the lbmd library runs on an MI355X (gfx950) only")
         self.replicas = list(replicas)
         self.storage = storage
-        self._cfg = Config(self.replicas, md, storage, init, block_size, flags, mapping, xcd_order, md_lanes)
+        self._cfg = Config(self.replicas, md, storage, init, block_size, flags, mapping, xcd_order, md_lanes,
+                           obs_every, obs_capacity)
         L = lib()
         self._bufs = None
         self._tensors = []
@@ -310,6 +318,14 @@ class Simulation:
     def transloc(self, replica: int = 0, allow_unstable: bool = False) -> dict:
         a = self._moments(replica, LB_MOM_TRANSLOC, allow_unstable)
         return {"n_t": int(a[0]), "t_done": int(a[1]), "com": a[2:5].copy(), "step": int(a[5])}
+
+    def observables(self, replica: int = 0, allow_unstable: bool = False):
+        """The recorded observable rows of a replica ([rows][8], columns OBS_COLUMNS) and the
+        number of rows the kernel counted (larger than rows when the record overflowed)."""
+        a = self._moments(replica, LB_MOM_OBSERVABLES, allow_unstable).reshape(-1, 8)
+        counted = int(a[0, 0])
+        kept = min(counted, len(a) - 1)
+        return a[1:1 + kept].copy(), counted
 
     def status(self):
         a = self._moments(0, LB_MOM_STATUS, allow_unstable=True)
