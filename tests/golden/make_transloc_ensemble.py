@@ -4,6 +4,9 @@ Every event is one replica of the 48^3 pore box of workloads.configs.ensemble48_
 translocation set-up of Sec. III at a reduced size): a 32-bead chain grown from the pore mouth
 with its own seed, advanced by FP64 coupled oracle steps until every bead lies past the wall's
 mid-plane (the completion step t_done) or the step cap is reached (t_done = -1, censored).
+After every step the oracle's translocation observables are taken (Sec. III: S_H, S_E, K,
+the radii of gyration of both sides); each event row also holds their means over the event
+(steps 1..t_done), the ratio R_T(t_done) / R_U(1), and whether the chain retracted.
 With --no-hydro the beads move alone in a fluid at rest (u = 0, no lattice, the no-solvent
 comparison of Sec. III) and the sample goes to transloc_pore48_n32_nohydro.txt.
 Only oracle/ and the seeded input generators of workloads/ are called.
@@ -41,9 +44,26 @@ def _event(args):
     f0 = O.equilibrium_populations(rep.box, np.full(rep.box.nodes, rep.box.rho0),
                                    np.zeros((3, rep.box.nodes)))
     sim = O.Sim(rep.box, w.md, rep.chain_len, f0, beads, None, seed=rep.seed)
+    obs = []
     while sim.t_done < 0 and sim.step_no < WC.ENSEMBLE_STEP_CAP:
-        sim.step(min(CHUNK, WC.ENSEMBLE_STEP_CAP - sim.step_no), hydro=hydro)
-    return rep.seed, sim.t_done, sim.flags
+        sim.step(1, hydro=hydro)
+        obs.append(sim.observables())
+    obs = np.array(obs)
+    n = rep.n_beads
+    # retraction: N_T reached max(2, N/10) and fell back to 0 (the analysis module's rule)
+    thr, seen, retr = max(2, n // 10), False, 0
+    for v in obs[:, 0]:
+        if v >= thr:
+            seen = True
+        elif seen and v == 0:
+            retr = 1
+            break
+    if sim.t_done > 0:
+        ev = obs[: sim.t_done]
+        extra = (ev[:, 1].mean(), ev[:, 2].mean(), ev[:, 3].mean(), np.sqrt(ev[-1, 5] / ev[0, 4]))
+    else:
+        extra = (float("nan"),) * 4
+    return (rep.seed, sim.t_done, sim.flags) + tuple(float(x) for x in extra) + (retr,)
 
 
 def main():
@@ -63,7 +83,8 @@ def main():
     with get_context("spawn").Pool(args.jobs) as pool:
         for i, row in enumerate(pool.imap(_event, [(k, hydro) for k in range(args.events)])):
             rows.append(row)
-            print(f"event {i}: seed {row[0]} t_done {row[1]} flags {row[2]} "
+            print(f"event {i}: seed {row[0]} t_done {row[1]} flags {row[2]} S_H {row[3]:.3e} "
+                  f"S_E {row[4]:.3e} K {row[5]:.3e} R_T/R_U {row[6]:.3f} retracted {row[7]} "
                   f"({time.time() - t0:.0f} s)", flush=True)
     md = WC.MDParams()
     with open(out, "w") as fh:
@@ -80,9 +101,11 @@ def main():
                  f"f_drive={md.f_drive}\n")
         fh.write(f"# seeds {WC.ENSEMBLE_SEED_ORACLE}+k; step cap {WC.ENSEMBLE_STEP_CAP}; "
                  "t_done = -1 marks a censored event\n")
-        fh.write("# seed t_done flags\n")
-        for seed, t, fl in rows:
-            fh.write(f"{seed} {t} {fl}\n")
+        fh.write("# per event: means over steps 1..t_done of S_H = m gamma sum v.u, S_E = sum "
+                 "F_drive.v, K = m/2 sum v^2; R_T(t_done)/R_U(1); retracted (0/1)\n")
+        fh.write("# seed t_done flags S_H S_E K R_T_end_over_R_U_start retracted\n")
+        for seed, t, fl, sh, se, ke, rr, retr in rows:
+            fh.write(f"{seed} {t} {fl} {sh:.10e} {se:.10e} {ke:.10e} {rr:.10e} {retr}\n")
     print(f"wrote {out}: {len(rows)} events in {time.time() - t0:.0f} s")
 
 

@@ -7,7 +7,11 @@ distribution of the completion step t_done (the first step at which every bead l
 wall's mid-plane, Sec. III).  The oracle's sample (FP64, stored in tests/golden by a script
 that calls only the oracle) and the GPU's sample come from disjoint seed ranges, so they are
 independent; the test asks for a two-sample Kolmogorov-Smirnov p-value above 0.01 and means
-within three combined standard errors, for every storage format.
+within three combined standard errors, for every storage format.  The same holds for the
+per-event observables of the translocation analysis (Sec. III), taken from the record the bead
+kernel writes every step: the means over the event of S_H, S_E and K, and the ratio R_T at
+completion over R_U after the first step (KS p above 0.001 and means within four standard
+errors, looser because four more quantities are tested per sample).
 """
 from __future__ import annotations
 
@@ -27,20 +31,30 @@ N_GPU = 512
 CHECK_EVERY = 250
 
 
-def oracle_times(path=GOLDEN) -> np.ndarray:
-    rows = np.loadtxt(path, comments="#", dtype=np.int64, ndmin=2)
+# columns of the stored sample: seed t_done flags S_H S_E K R_T_end_over_R_U_start retracted
+OBS_COLS = {"S_H": 3, "S_E": 4, "K": 5, "R_ratio": 6}
+
+
+def oracle_rows(path=GOLDEN) -> np.ndarray:
+    rows = np.loadtxt(path, comments="#", ndmin=2)
     assert np.all(rows[:, 2] == 0), "the oracle ensemble holds an event with error flags"
-    return rows[:, 1]
+    return rows
+
+
+def oracle_times(path=GOLDEN) -> np.ndarray:
+    return oracle_rows(path)[:, 1].astype(np.int64)
 
 
 @pytest.mark.parametrize("path", [GOLDEN, GOLDEN_NO_HYDRO], ids=["coupled", "nohydro"])
 def test_oracle_ensemble_file(path):
     """The stored sample is complete, uncensored and drawn from the oracle seed range."""
-    rows = np.loadtxt(path, comments="#", dtype=np.int64, ndmin=2)
-    assert len(rows) >= 64
-    assert np.array_equal(rows[:, 0], WC.ENSEMBLE_SEED_ORACLE + np.arange(len(rows)))
+    rows = np.loadtxt(path, comments="#", ndmin=2)
+    assert len(rows) >= 64 and rows.shape[1] == 8
+    assert np.array_equal(rows[:, 0].astype(np.int64), WC.ENSEMBLE_SEED_ORACLE + np.arange(len(rows)))
     t = rows[:, 1]
     assert np.all(t > 0) and np.all(t < WC.ENSEMBLE_STEP_CAP)
+    assert np.all(np.isfinite(rows[:, 3:7]))
+    assert np.all(rows[:, 5] > 0) and np.all(rows[:, 6] > 0)
 
 
 def test_solvent_speeds_translocation():
@@ -63,7 +77,7 @@ def test_translocation_time_distribution(storage, hydro):
     log(f"ensemble {w.name} storage {WC.STORE_NAMES[storage]}{'' if hydro else ' without solvent'}: "
         f"{N_GPU} replicas, cap {WC.ENSEMBLE_STEP_CAP} steps")
     beads = np.concatenate(G.workload_beads(w))
-    sim = gpu_sim(w.replicas, w.md, storage, beads=beads)
+    sim = gpu_sim(w.replicas, w.md, storage, beads=beads, obs_every=1, obs_capacity=WC.ENSEMBLE_STEP_CAP)
     try:
         steps = 0
         t_gpu = np.full(N_GPU, -1)
@@ -77,6 +91,7 @@ def test_translocation_time_distribution(storage, hydro):
                 break
         err, _ = sim.status()
         assert err == 0, f"error word {err:#x}"
+        records = [sim.observables(r)[0] for r in range(N_GPU)]
     finally:
         sim.close()
     assert np.all(t_gpu > 0), f"{int(np.sum(t_gpu < 0))} GPU events censored at the step cap"
@@ -88,3 +103,26 @@ def test_translocation_time_distribution(storage, hydro):
         f"mean difference {abs(m_g - m_o) / se:.2f} standard errors")
     assert ks.pvalue > 0.01
     assert abs(m_g - m_o) < 3.0 * se
+
+    # per-event observables of the Sec. III analysis
+    from paper_0710_1272_amd import ensemble as E
+    ora = oracle_rows(GOLDEN if hydro else GOLDEN_NO_HYDRO)
+    gpu = {k: [] for k in OBS_COLS}
+    for rows, t in zip(records, t_gpu):
+        ev = E.event_rows(rows, int(t))
+        assert len(ev) == t and ev[-1, E.STEP] == t
+        gpu["S_H"].append(ev[:, E.S_H].mean())
+        gpu["S_E"].append(ev[:, E.S_E].mean())
+        gpu["K"].append(ev[:, E.K].mean())
+        gpu["R_ratio"].append(np.sqrt(ev[-1, E.R_T2] / ev[0, E.R_U2]))
+    for key, col in OBS_COLS.items():
+        a, b = np.array(gpu[key]), ora[:, col]
+        if not hydro and key == "S_H":
+            assert np.all(a == 0.0) and np.all(b == 0.0)  # no solvent: no fluid work
+            continue
+        ks = stats.ks_2samp(a, b)
+        se = np.sqrt(a.var(ddof=1) / len(a) + b.var(ddof=1) / len(b))
+        log(f"  {key}: gpu {a.mean():.4e} oracle {b.mean():.4e}; KS p {ks.pvalue:.4f}; "
+            f"{abs(a.mean() - b.mean()) / se:.2f} standard errors")
+        assert ks.pvalue > 0.001, key
+        assert abs(a.mean() - b.mean()) < 4.0 * se, key
