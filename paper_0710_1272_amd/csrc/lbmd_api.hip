@@ -511,6 +511,7 @@ hipError_t enqueue_step(Context& c, int mode, int cur, hipStream_t main) {
         // beads alone; the counter moves in its own launch, after every replica has read it
         hipError_t e;
         if (c.ntot_beads > 0 && (e = launch_md(c, src, MD_SUBSTEPS | MD_NO_HYDRO, main)) != hipSuccess) return e;
+        if (c.ntot_beads > 0 && c.obs_every > 0 && (e = launch_observe(c, true, main)) != hipSuccess) return e;
         return launch_bump(c, main);
     }
     const bool coupled = mode == STEP_COUPLED;
@@ -519,6 +520,7 @@ hipError_t enqueue_step(Context& c, int mode, int cur, hipStream_t main) {
         if ((e = hipEventRecord(c.ev_fork, main)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(c.side, c.ev_fork, 0)) != hipSuccess) return e;
         if ((e = launch_md(c, src, MD_COUPLED, c.side)) != hipSuccess) return e;
+        if (c.obs_every > 0 && (e = launch_observe(c, false, c.side)) != hipSuccess) return e;
         if ((e = hipEventRecord(c.ev_join, c.side)) != hipSuccess) return e;
         if ((e = launch_stream_collide(c, src, dst, false, main)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(main, c.ev_join, 0)) != hipSuccess) return e;
@@ -834,6 +836,7 @@ int md_step(lbmd_ctx* ctx) {
     Context& c = ctx->c;
     if (c.ntot_beads == 0) return LB_OK;
     HIP_TRY(launch_md(c, c.pops[c.cur], MD_SUBSTEPS, c.stream));
+    if (c.obs_every > 0) HIP_TRY(launch_observe(c, false, c.stream));
     return LB_OK;
 }
 

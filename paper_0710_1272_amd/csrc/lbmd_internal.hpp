@@ -114,6 +114,9 @@ hipError_t launch_conserved(const Context& c, int r, const void* src, double* d_
 hipError_t launch_md(const Context& c, const void* cur, int mode, hipStream_t s);
 hipError_t launch_spread(const Context& c, void* dst, bool bump_step, hipStream_t s);
 hipError_t launch_bump(const Context& c, hipStream_t s);
+// appends a row to every replica's observable record after a bead step, when the new step
+// count is a multiple of obs_every (no_hydro: the beads saw a fluid at rest, u = 0)
+hipError_t launch_observe(const Context& c, bool no_hydro, hipStream_t s);
 int md_default_lanes(int max_beads);
 bool md_lanes_valid(int lanes, int max_beads);
 

@@ -335,15 +335,18 @@ __device__ __forceinline__ void angle_forces(const double* ra, const double* rb,
 // One tridiagonal system a_t x_{t-1} + b_t x_t + c_t x_{t+1} = d_t per workgroup, row t
 // held by thread t (t < m), solved by parallel cyclic reduction: at stride s each row
 // eliminates its couplings to rows t - s and t + s (rows outside 0..m-1 are identities),
-// so after ceil(log2 m) levels x_t = d_t / b_t.  Double-buffered in LDS (W: [2][4][nmax]
-// doubles: a, b, c, d); one barrier per level.  Every thread of the block must call it.
+// so after ceil(log2 m) levels x_t = d_t / b_t.  Each row publishes 1/b with a, c, d, so a
+// level takes one division (the row's own new 1/b) instead of two.  Double-buffered in LDS
+// (W: [2][4][nmax] doubles: a, 1/b, c, d); one barrier per level.  Every thread of the
+// block must call it.
 __device__ __forceinline__ double pcr_solve(double* W, int nmax, int m, int t, double a, double b, double c,
                                             double d) {
     const bool row = t < m;
     int buf = 0;
+    double ib = 1.0 / b;
     if (row) {
         W[(0 * 4 + 0) * nmax + t] = a;
-        W[(0 * 4 + 1) * nmax + t] = b;
+        W[(0 * 4 + 1) * nmax + t] = ib;
         W[(0 * 4 + 2) * nmax + t] = c;
         W[(0 * 4 + 3) * nmax + t] = d;
     }
@@ -353,25 +356,26 @@ __device__ __forceinline__ double pcr_solve(double* W, int nmax, int m, int t, d
         double* Wd = W + (buf ^ 1) * 4 * nmax;
         if (row) {
             const int lo = t - s, hi = t + s;
-            const double al = lo >= 0 ? Ws[lo] : 0.0, bl = lo >= 0 ? Ws[nmax + lo] : 1.0;
+            const double al = lo >= 0 ? Ws[lo] : 0.0, ibl = lo >= 0 ? Ws[nmax + lo] : 1.0;
             const double cl = lo >= 0 ? Ws[2 * nmax + lo] : 0.0, dl = lo >= 0 ? Ws[3 * nmax + lo] : 0.0;
-            const double ah = hi < m ? Ws[hi] : 0.0, bh = hi < m ? Ws[nmax + hi] : 1.0;
+            const double ah = hi < m ? Ws[hi] : 0.0, ibh = hi < m ? Ws[nmax + hi] : 1.0;
             const double ch = hi < m ? Ws[2 * nmax + hi] : 0.0, dh = hi < m ? Ws[3 * nmax + hi] : 0.0;
-            const double k1 = a / bl, k2 = c / bh;
+            const double k1 = a * ibl, k2 = c * ibh;
             const double na = -al * k1, nc = -ch * k2;
             b = b - cl * k1 - ah * k2;
             d = d - dl * k1 - dh * k2;
             a = na;
             c = nc;
+            ib = 1.0 / b;
             Wd[t] = a;
-            Wd[nmax + t] = b;
+            Wd[nmax + t] = ib;
             Wd[2 * nmax + t] = c;
             Wd[3 * nmax + t] = d;
         }
         buf ^= 1;
         __syncthreads();
     }
-    return row ? d / b : 0.0;
+    return row ? d * ib : 0.0;
 }
 
 // Verlet-list entries each lane keeps in registers (slot s of lane gl is entry gl + s G);
@@ -450,7 +454,7 @@ __device__ __forceinline__ int build_list(int i, int n, bool bn, bool bp, const 
 template <class Real, int G, int BPT, bool PERIODIC, int MAXT, bool POLY>
 __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
     extern __shared__ double lds[];
-    __shared__ double red[16 * 8];
+    __shared__ double red[16 * 4];
     const int NG = blockDim.x / G;  // groups per block
     const Replica& R = a.reps[blockIdx.x];
     const Geom GM = load_geom(R);
@@ -1104,72 +1108,6 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
     }
     block_sums<Real>(acc, 4, red);
 
-    // observable record of the translocation analysis (Sec. III), one row every obs_every
-    // steps: work rates S_H = m gamma sum v.u and S_E = sum F_drive.v, kinetic energy, and
-    // the radii of gyration of the two sides of the wall from FP64 sums of positions taken
-    // relative to the pore centre (which keeps the second moments small)
-    if (a.b.obs_every > 0 && (a.mode & MD_SUBSTEPS) && (step + 1) % a.b.obs_every == 0) {
-        const double ref[3] = {xmid, 0.5 * nd[1], 0.5 * nd[2]};
-        double o[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // S_H, S_E, K, sum d^2, trans: sum d (3), sum d^2
-#pragma unroll
-        for (int k = 0; k < BPT; ++k) {
-            if (!own[k] || gl != 0) continue;
-            double vu = 0.0, vv = 0.0, d2 = 0.0, dd[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                vu += (double)v[k][c] * (double)u[k][c];
-                vv += (double)v[k][c] * (double)v[k][c];
-                dd[c] = r[k][c] - ref[c];
-                d2 += dd[c] * dd[c];
-            }
-            bool pore = false;
-#pragma unroll
-            for (int w = 0; w < LB_MAX_WALLS; ++w) {
-                if (w >= GM.n_walls) break;
-                pore = pore || wall_pore_node<PERIODIC>(GM, GM.wall[w], r[k]);
-            }
-            o[0] += md.mass * md.gamma * vu;
-            o[1] += pore ? md.f_drive * (double)v[k][0] : 0.0;
-            o[2] += 0.5 * md.mass * vv;
-            o[3] += d2;
-            if (r[k][0] > xmid) {
-                o[4] += dd[0];
-                o[5] += dd[1];
-                o[6] += dd[2];
-                o[7] += d2;
-            }
-        }
-        block_sums<Real>(o, 8, red);
-        if (tid == 0) {
-            double* rec = a.b.obs + (size_t)blockIdx.x * ((size_t)a.b.obs_cap + 1) * 8;
-            const double cnt = rec[0];
-            if (cnt < (double)a.b.obs_cap) {
-                const double nT = acc[0], nU = (double)n - acc[0];
-                // all-bead sums of d = r - ref from the position sums
-                const double sa[3] = {acc[1] - n * ref[0], acc[2] - n * ref[1], acc[3] - n * ref[2]};
-                double rT = 0.0, rU = 0.0;
-                if (nT > 0) {
-                    const double c0 = o[4] / nT, c1 = o[5] / nT, c2 = o[6] / nT;
-                    rT = fmax(o[7] / nT - (c0 * c0 + c1 * c1 + c2 * c2), 0.0);
-                }
-                if (nU > 0) {
-                    const double c0 = (sa[0] - o[4]) / nU, c1 = (sa[1] - o[5]) / nU, c2 = (sa[2] - o[6]) / nU;
-                    rU = fmax((o[3] - o[7]) / nU - (c0 * c0 + c1 * c1 + c2 * c2), 0.0);
-                }
-                double* row = rec + (size_t)(1 + (long long)cnt) * 8;
-                row[0] = (double)(step + 1);
-                row[1] = nT;
-                row[2] = o[0];
-                row[3] = o[1];
-                row[4] = o[2];
-                row[5] = rU;
-                row[6] = rT;
-                row[7] = acc[1] / n;
-            }
-            rec[0] = cnt + 1.0;
-        }
-    }
-
     // one leader per occupied node (its lowest-index bead) sums the Fbar of the beads on
     // it in index order; a bead alone on its node is its own sum
     double* FX = P;  // positions are no longer needed
@@ -1268,13 +1206,99 @@ __global__ __launch_bounds__(256) void k_spread(const Replica* __restrict__ reps
 
 __global__ void k_bump(RunState* st) { st->step += 1; }
 
+// Observable record of the translocation analysis (Sec. III), one workgroup per replica,
+// after the bead step and before the step counter moves: when (step + 1) is a multiple of
+// obs_every, a row (step + 1, N_T, S_H = m gamma sum v.u, S_E = sum F_drive.v over beads on
+// pore nodes, K = m/2 sum v^2, R_U^2, R_T^2, x of the centre of mass) is appended to the
+// replica's record (rows beyond the capacity are counted, not kept).  FP64 sums in a fixed
+// order; positions are taken relative to the pore centre, which keeps the second moments of
+// the radii of gyration small.
+template <class Real>
+__global__ __launch_bounds__(256) void k_observe(const Replica* __restrict__ reps, BeadPtrs<Real> b,
+                                                 const RunState* __restrict__ st, double mass_gamma,
+                                                 double half_mass, double f_drive, int no_hydro) {
+    __shared__ double red[16 * 12];
+    const long long step = st->step;
+    if ((step + 1) % b.obs_every != 0) return;
+    const Replica& R = reps[blockIdx.x];
+    const int n = R.n_beads;
+    if (n == 0) return;
+    const Geom GM = load_geom(R);
+    const int b0 = R.bead0, NT = b.ntot;
+    const double xmid = R.xmid;
+    const double ref[3] = {xmid, 0.5 * R.ny, 0.5 * R.nz};
+    // N_T, S_H, S_E, K, sum d (3), sum d^2, and over the translocated beads sum d (3), sum d^2
+    double o[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int g = b0 + i;
+        double r[3], v[3], u[3], d[3], d2 = 0.0, vu = 0.0, vv = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            r[c] = b.r[c * NT + g];
+            v[c] = (double)b.v[c * NT + g];
+            u[c] = no_hydro ? 0.0 : (double)b.u[c * NT + g];
+            d[c] = r[c] - ref[c];
+            d2 += d[c] * d[c];
+            vu += v[c] * u[c];
+            vv += v[c] * v[c];
+        }
+        bool pore = false;
+#pragma unroll
+        for (int w = 0; w < LB_MAX_WALLS; ++w) {
+            if (w >= GM.n_walls) break;
+            pore = pore || wall_pore_node<true>(GM, GM.wall[w], r);
+        }
+        const bool tr = r[0] > xmid;
+        o[0] += tr ? 1.0 : 0.0;
+        o[1] += mass_gamma * vu;
+        o[2] += pore ? f_drive * v[0] : 0.0;
+        o[3] += half_mass * vv;
+        o[4] += d[0];
+        o[5] += d[1];
+        o[6] += d[2];
+        o[7] += d2;
+        if (tr) {
+            o[8] += d[0];
+            o[9] += d[1];
+            o[10] += d[2];
+            o[11] += d2;
+        }
+    }
+    block_sums<Real>(o, 12, red);
+    if (threadIdx.x != 0) return;
+    double* rec = b.obs + (size_t)blockIdx.x * ((size_t)b.obs_cap + 1) * 8;
+    const double cnt = rec[0];
+    if (cnt < (double)b.obs_cap) {
+        const double nT = o[0], nU = (double)n - o[0];
+        double rT = 0.0, rU = 0.0;
+        if (nT > 0) {
+            const double c0 = o[8] / nT, c1 = o[9] / nT, c2 = o[10] / nT;
+            rT = fmax(o[11] / nT - (c0 * c0 + c1 * c1 + c2 * c2), 0.0);
+        }
+        if (nU > 0) {
+            const double c0 = (o[4] - o[8]) / nU, c1 = (o[5] - o[9]) / nU, c2 = (o[6] - o[10]) / nU;
+            rU = fmax((o[7] - o[11]) / nU - (c0 * c0 + c1 * c1 + c2 * c2), 0.0);
+        }
+        double* row = rec + (size_t)(1 + (long long)cnt) * 8;
+        row[0] = (double)(step + 1);
+        row[1] = nT;
+        row[2] = o[1];
+        row[3] = o[2];
+        row[4] = o[3];
+        row[5] = rU;
+        row[6] = rT;
+        row[7] = ref[0] + o[4] / n;
+    }
+    rec[0] = cnt + 1.0;
+}
+
 // ---------------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------------
 static int md_nmax(const Context& c) { return (c.max_beads + 63) / 64 * 64; }
 
 static constexpr size_t kMDLdsBudget = 150 * 1024;
-// the bead kernel's static LDS (block sums 1 KB, rebuild vote 32 B) stays below this
+// the bead kernel's static LDS (block sums 512 B, rebuild vote 32 B) stays below this
 static constexpr int kMDStaticLds = 2048;
 
 static size_t md_base_lds(size_t nmax) { return nmax * (6 * sizeof(double) + sizeof(int) + 1); }
@@ -1408,6 +1432,20 @@ hipError_t launch_spread(const Context& c, void* dst, bool bump, hipStream_t s) 
         case LB_STORE_BF16DEV: return launch_spread_t<LB_STORE_BF16DEV>(c, dst, bump, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+template <class Real>
+static hipError_t launch_observe_t(const Context& c, bool no_hydro, hipStream_t s) {
+    const BeadPtrs<Real> b = *(const BeadPtrs<Real>*)c.bead_ptrs;
+    hipLaunchKernelGGL((k_observe<Real>), dim3((unsigned)c.reps.size()), dim3(256), 0, s, c.d_reps, b, c.d_state,
+                       c.md.mass * c.md.gamma, 0.5 * c.md.mass, c.md.f_drive, no_hydro ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_observe(const Context& c, bool no_hydro, hipStream_t s) {
+    if (c.obs_every <= 0 || c.ntot_beads == 0) return hipSuccess;
+    return c.storage == LB_STORE_F64 ? launch_observe_t<double>(c, no_hydro, s)
+                                     : launch_observe_t<float>(c, no_hydro, s);
 }
 
 hipError_t launch_bump(const Context& c, hipStream_t s) {
