@@ -155,6 +155,8 @@ def run_length(box, md, n_beads: int, events: int, seed0: int, storage: int, ste
             sim.step(n, hydro=hydro)
             steps += n
             t_done = np.array([sim.transloc(r)["t_done"] for r in range(events)])
+            if steps % (10 * check_every) == 0:
+                log(f"    N={n_beads} step {steps}: {int(np.sum(t_done >= 0))}/{events} completed")
             if np.all(t_done >= 0):
                 break
         err, _ = sim.status()
