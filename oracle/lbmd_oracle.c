@@ -111,6 +111,7 @@ typedef struct {
     double kappa_phi;         /* angular term kappa_phi phi^2 / 2 between consecutive bonds */
     double shake_tol;         /* rigid bonds: |s^2 - r0^2| <= shake_tol r0^2 */
     int shake_iter;           /* rigid bonds: most Newton iterations per substep */
+    int stencil;              /* coupling stencil: 0 nearest node, 1 trilinear over the 8 surrounding nodes */
 } ora_md;
 
 enum { ORA_BEAD_IN_SOLID = 1, ORA_BEAD_OUTSIDE = 2, ORA_NONFINITE = 4, ORA_BOND_STRETCH = 8,
@@ -451,6 +452,87 @@ void ora_interp(const ora_box* b, const double* f, int n, const double* r, doubl
         u[3 * i] = j[0] / rho;
         u[3 * i + 1] = j[1] / rho;
         u[3 * i + 2] = j[2] / rho;
+    }
+}
+
+/* Trilinear stencil of a position, the flagged variant of steps 1 and 3 (the fluid
+ * velocity taken from, and the force given back to, the nodes surrounding the bead): the
+ * 8 nodes floor(r_a) + {0, 1} per axis with weights prod_a (1 - |r_a - x_a|), which sum to
+ * one.  A periodic axis wraps the node index; on a free-slip axis a node outside the box
+ * (index -1 or n, for a bead within half a node of a face) is the mirror image of the face
+ * node across the face plane, i.e. the face node itself. */
+static void trilinear_stencil(const ora_box* b, const double* r, int node[8][3], double wt[8])
+{
+    const int n[3] = {b->nx, b->ny, b->nz};
+    int lo[3][2];
+    double w1[3][2];
+    for (int a = 0; a < 3; ++a) {
+        double t = floor(r[a]);
+        if (!(t >= -1e9 && t <= 1e9)) t = 0.0; /* non-finite positions */
+        const double fr = r[a] - t;
+        w1[a][0] = 1.0 - fr;
+        w1[a][1] = fr;
+        for (int s = 0; s < 2; ++s) {
+            long k = (long)t + s;
+            if (b->bc[a] == 0) {
+                k %= n[a];
+                if (k < 0) k += n[a];
+            } else {
+                if (k < 0) k = 0;
+                if (k > n[a] - 1) k = n[a] - 1;
+            }
+            lo[a][s] = (int)k;
+        }
+    }
+    for (int c = 0; c < 8; ++c) {
+        const int sx = c & 1, sy = (c >> 1) & 1, sz = (c >> 2) & 1;
+        node[c][0] = lo[0][sx];
+        node[c][1] = lo[1][sy];
+        node[c][2] = lo[2][sz];
+        wt[c] = w1[0][sx] * w1[1][sy] * w1[2][sz];
+    }
+}
+
+/* Step 1 with the trilinear stencil: u_i = sum_c wt_c u(x_c), u = j / rho at fluid nodes and
+ * 0 at solid ones. */
+void ora_interp_trilinear(const ora_box* b, const double* f, int n, const double* r, double* u)
+{
+    const long V = (long)b->nx * b->ny * b->nz;
+    for (int i = 0; i < n; ++i) {
+        int nd[8][3];
+        double wt[8];
+        trilinear_stencil(b, r + 3 * i, nd, wt);
+        u[3 * i] = u[3 * i + 1] = u[3 * i + 2] = 0.0;
+        for (int c = 0; c < 8; ++c) {
+            if (ora_is_solid(b, nd[c][0], nd[c][1], nd[c][2])) continue;
+            long k = node_index(b, nd[c][0], nd[c][1], nd[c][2]);
+            double fp[Q], rho, j[3];
+            for (int p = 0; p < Q; ++p) fp[p] = f[(long)p * V + k];
+            node_moments(fp, &rho, j);
+            for (int a = 0; a < 3; ++a) u[3 * i + a] += wt[c] * j[a] / rho;
+        }
+    }
+}
+
+/* Step 3 with the trilinear stencil: S_p(x_c) += -wt_c (w_p / cs^2) Fbar_i . c_p at every
+ * fluid node x_c of the stencil of the start-of-step position r (shares on solid nodes
+ * are dropped, as a nearest node on a solid node drops the whole force). */
+void ora_spread_trilinear(const ora_box* b, int n, const double* r, const double* fbar, double* S)
+{
+    const long V = (long)b->nx * b->ny * b->nz;
+    for (int i = 0; i < n; ++i) {
+        int nd[8][3];
+        double wt[8];
+        trilinear_stencil(b, r + 3 * i, nd, wt);
+        for (int c = 0; c < 8; ++c) {
+            if (ora_is_solid(b, nd[c][0], nd[c][1], nd[c][2])) continue;
+            long k = node_index(b, nd[c][0], nd[c][1], nd[c][2]);
+            for (int p = 0; p < Q; ++p) {
+                double fc = fbar[3 * i] * CV[p][0] + fbar[3 * i + 1] * CV[p][1] +
+                            fbar[3 * i + 2] * CV[p][2];
+                S[(long)p * V + k] += -wt[c] * (weight(p) / CS2) * fc;
+            }
+        }
     }
 }
 
@@ -984,9 +1066,21 @@ int ora_coupled_step(const ora_box* b, const ora_md* md, int n, int n_chains, co
 {
     const long V = (long)b->nx * b->ny * b->nz;
     ora_interp(b, f, n, r, u, node);
+    double* r_start = NULL;
+    if (md->stencil == 1) {
+        /* the trilinear stencil of the start-of-step positions, for both halves */
+        ora_interp_trilinear(b, f, n, r, u);
+        r_start = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+        memcpy(r_start, r, sizeof(double) * 3 * (size_t)n);
+    }
     int flags = ora_md_substeps(b, md, n, n_chains, chain_len, r, v, u, fbar, step, seed);
     memset(S, 0, sizeof(double) * Q * (size_t)V);
-    ora_spread(b, n, node, fbar, S);
+    if (md->stencil == 1) {
+        ora_spread_trilinear(b, n, r_start, fbar, S);
+        free(r_start);
+    } else {
+        ora_spread(b, n, node, fbar, S);
+    }
     if (ora_lb_step(b, f, work, S, step, seed) > 0) flags |= 16;
     return flags;
 }

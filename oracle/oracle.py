@@ -44,7 +44,8 @@ class _MD(C.Structure):
                 ("k_bond", C.c_double), ("r0", C.c_double), ("eps", C.c_double),
                 ("sigma", C.c_double), ("eps_w", C.c_double), ("sigma_w", C.c_double),
                 ("f_drive", C.c_double), ("drive_sign", C.c_int), ("rigid", C.c_int),
-                ("kappa_phi", C.c_double), ("shake_tol", C.c_double), ("shake_iter", C.c_int)]
+                ("kappa_phi", C.c_double), ("shake_tol", C.c_double), ("shake_iter", C.c_int),
+                ("stencil", C.c_int)]
 
 
 _lib = None
@@ -74,6 +75,8 @@ def lib():
         L.ora_philox.argtypes = [up, up, up]
         L.ora_interp.argtypes = [bp, dp, C.c_int, dp, dp, lp]
         L.ora_spread.argtypes = [bp, C.c_int, lp, dp, dp]
+        L.ora_interp_trilinear.argtypes = [bp, dp, C.c_int, dp, dp]
+        L.ora_spread_trilinear.argtypes = [bp, C.c_int, dp, dp, dp]
         L.ora_wall_distance.argtypes = [bp, dp, dp]
         L.ora_wall_distance.restype = C.c_double
         L.ora_conservative_forces.argtypes = [bp, mp, C.c_int, C.c_int, ip, dp, dp]
@@ -244,6 +247,24 @@ def interp(box, f: np.ndarray, r: np.ndarray):
     b = make_box(box)
     lib().ora_interp(C.byref(b), _dp(f), n, _dp(np.ascontiguousarray(r)), _dp(u), _lp(node))
     return u, node
+
+
+def interp_trilinear(box, f: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """Fluid velocity at the beads from the 8 surrounding nodes (trilinear weights)."""
+    n = len(r)
+    u = np.zeros((n, 3))
+    lib().ora_interp_trilinear(C.byref(make_box(box)), _dp(f), n, _dp(np.ascontiguousarray(r, dtype=np.float64)),
+                               _dp(u))
+    return u
+
+
+def spread_trilinear(box, r: np.ndarray, fbar: np.ndarray, S: Optional[np.ndarray] = None) -> np.ndarray:
+    """Reaction sources S_p on the 8 nodes around each start-of-step position r."""
+    if S is None:
+        S = np.zeros((Q, box.nodes))
+    lib().ora_spread_trilinear(C.byref(make_box(box)), len(r), _dp(np.ascontiguousarray(r, dtype=np.float64)),
+                               _dp(np.ascontiguousarray(fbar, dtype=np.float64)), _dp(S))
+    return S
 
 
 def spread(box, node: np.ndarray, fbar: np.ndarray, S: Optional[np.ndarray] = None) -> np.ndarray:

@@ -68,6 +68,7 @@ class MDParams:
     kappa_phi: float = 0.0     # angular term between consecutive bonds
     shake_tol: float = 1e-12   # rigid bonds: |s^2 - r0^2| <= shake_tol r0^2
     shake_iter: int = 30       # rigid bonds: most Newton iterations per substep
+    stencil: int = 0           # coupling stencil: 0 nearest node, 1 trilinear (8 surrounding nodes)
 
 
 def paper_polymer(**kw) -> MDParams:
