@@ -108,7 +108,17 @@ typedef struct lbmd_md_params {
     double shake_tol;  /* rigid bonds: |s^2 - r0^2| <= shake_tol r0^2 for every bond */
     int shake_iter;    /* rigid bonds: most Newton iterations per substep; not converging
                           sets LB_ERR_CONSTRAINT */
+    int stencil;       /* coupling stencil of steps 1 and 3 (Sec. II): LB_STENCIL_* */
 } lbmd_md_params;
+
+/* stencil: the node(s) a bead takes the fluid velocity from and gives its reaction to */
+#define LB_STENCIL_NGP 0       /* the nearest node floor(r + 1/2) (Sec. II, Fig. 1) */
+#define LB_STENCIL_TRILINEAR 1 /* the 8 surrounding nodes floor(r_a) + {0, 1}, weights
+                                  prod_a (1 - |r_a - x_a|); periodic axes wrap, a node beyond a
+                                  free-slip face is the face node; solid nodes give u = 0 and
+                                  drop their share of the reaction; the reaction uses the
+                                  stencil of the start-of-step position.  LB_MOM_COUPLING then
+                                  reports node -1 for every bead */
 
 /* Optional initial state (host arrays, read during lb_init only). */
 typedef struct lbmd_initial_state {

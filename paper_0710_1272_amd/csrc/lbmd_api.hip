@@ -119,6 +119,7 @@ BeadLayout bead_layout(int ntot, int n_reps, size_t rs, int obs_rows) {
     L.nlist = off;    off += align256((size_t)kNeighbourMax * N * sizeof(unsigned short));
     L.ncount = off;   off += align256(N * sizeof(int));
     L.rref = off;     off += align256(3 * N * sizeof(double));
+    L.rs = off;       off += align256(3 * N * sizeof(double));
     L.obs = off;      off += align256((size_t)std::max(n_reps, 1) * (size_t)obs_rows * 8 * sizeof(double));
     L.total = off;
     return L;
@@ -207,6 +208,8 @@ int lb_validate_config(const lbmd_config* cfg) {
             !std::isfinite(m.f_drive))
             return fail(LB_EINVAL, "md parameters out of range");
         if (m.drive_sign != 1 && m.drive_sign != -1) return fail(LB_EINVAL, "md.drive_sign must be +-1");
+        if (m.stencil != LB_STENCIL_NGP && m.stencil != LB_STENCIL_TRILINEAR)
+            return fail(LB_EINVAL, "md.stencil must be LB_STENCIL_NGP or LB_STENCIL_TRILINEAR");
         if (m.rigid != 0 && m.rigid != 1) return fail(LB_EINVAL, "md.rigid must be 0 or 1");
         if (!(m.kappa_phi >= 0) || !std::isfinite(m.kappa_phi)) return fail(LB_EINVAL, "md.kappa_phi must be >= 0");
         if (m.rigid) {
@@ -270,6 +273,7 @@ int setup_beads(Context& c, const lbmd_config* cfg) {
     p->nlist = (unsigned short*)(base + L.nlist);
     p->ncount = (int*)(base + L.ncount);
     p->rref = (double*)(base + L.rref);
+    p->rs = (double*)(base + L.rs);
     p->obs = (double*)(base + L.obs);
     p->obs_every = c.obs_every;
     p->obs_cap = c.obs_capacity;
@@ -519,7 +523,12 @@ hipError_t enqueue_step(Context& c, int mode, int cur, hipStream_t main) {
         hipError_t e;
         if ((e = hipEventRecord(c.ev_fork, main)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(c.side, c.ev_fork, 0)) != hipSuccess) return e;
-        if ((e = launch_md(c, src, MD_COUPLED, c.side)) != hipSuccess) return e;
+        if (c.md.stencil == LB_STENCIL_TRILINEAR) {
+            if ((e = launch_interp_trilinear(c, src, c.side)) != hipSuccess) return e;
+            if ((e = launch_md(c, src, MD_SUBSTEPS, c.side)) != hipSuccess) return e;
+        } else if ((e = launch_md(c, src, MD_COUPLED, c.side)) != hipSuccess) {
+            return e;
+        }
         if (c.obs_every > 0 && (e = launch_observe(c, false, c.side)) != hipSuccess) return e;
         if ((e = hipEventRecord(c.ev_join, c.side)) != hipSuccess) return e;
         if ((e = launch_stream_collide(c, src, dst, false, main)) != hipSuccess) return e;
@@ -671,6 +680,7 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
     md.rigid = m.rigid;
     md.shake_iter = m.shake_iter;
     md.kappa_phi = m.kappa_phi;
+    md.stencil = m.stencil;
     md.b2 = m.r0 * m.r0;
     md.shake_tol_b2 = m.shake_tol * md.b2;
 
@@ -826,7 +836,9 @@ int lb_couple(lbmd_ctx* ctx, unsigned dir) {
     Context& c = ctx->c;
     if (dir != LB_COUPLE_INTERP && dir != LB_COUPLE_SPREAD) return fail(LB_EINVAL, "unknown direction");
     if (c.ntot_beads == 0) return LB_OK;
-    if (dir == LB_COUPLE_INTERP) HIP_TRY(launch_md(c, c.pops[c.cur], MD_INTERP, c.stream));
+    if (dir == LB_COUPLE_INTERP && c.md.stencil == LB_STENCIL_TRILINEAR)
+        HIP_TRY(launch_interp_trilinear(c, c.pops[c.cur], c.stream));
+    else if (dir == LB_COUPLE_INTERP) HIP_TRY(launch_md(c, c.pops[c.cur], MD_INTERP, c.stream));
     else HIP_TRY(launch_spread(c, c.pops[c.cur], false, c.stream));
     return LB_OK;
 }

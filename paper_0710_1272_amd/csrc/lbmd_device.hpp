@@ -350,6 +350,7 @@ struct BeadPtrs {
     int* ncount;        // [Ntot] number of neighbours; > kNeighbourMax means overflow
     double* rref;       // [3][Ntot] positions at the last list build (lists are kept across
                         // LB steps while diag[7] of the replica is 1)
+    double* rs;         // [3][Ntot] start-of-step positions (trilinear stencil of the spread)
     double* obs;        // [n_replicas][obs_cap + 1][8] observable record (header row first)
     int obs_every, obs_cap;
     int ntot;

@@ -24,6 +24,7 @@ struct MDDev {
     int rigid;                        // rigid bonds (SHAKE/RATTLE) instead of harmonic ones
     int shake_iter;
     double kappa_phi;                 // angular term between consecutive bonds
+    int stencil;                      // LB_STENCIL_*
     double b2, shake_tol_b2;          // rigid bond length^2 and the SHAKE tolerance on |s^2 - b^2|
 };
 
@@ -98,7 +99,7 @@ WorkLayout work_layout(int n_reps, int max_V, long long max_stage_nodes);
 
 // bead-buffer layout
 struct BeadLayout {
-    size_t r, v, u, fbar, node, bond_next, agg_at, agg_f, rep_of, diag, nlist, ncount, rref, obs, total;
+    size_t r, v, u, fbar, node, bond_next, agg_at, agg_f, rep_of, diag, nlist, ncount, rref, rs, obs, total;
 };
 // obs_rows: rows of the observable record per replica (capacity + 1 header row; 0 = none)
 BeadLayout bead_layout(int ntot, int n_reps, size_t real_size, int obs_rows);
@@ -114,6 +115,9 @@ hipError_t launch_conserved(const Context& c, int r, const void* src, double* d_
 hipError_t launch_md(const Context& c, const void* cur, int mode, hipStream_t s);
 hipError_t launch_spread(const Context& c, void* dst, bool bump_step, hipStream_t s);
 hipError_t launch_bump(const Context& c, hipStream_t s);
+// step 1 with the trilinear stencil (a kernel of its own; the bead kernel then runs its
+// substeps on the interpolated velocities)
+hipError_t launch_interp_trilinear(const Context& c, const void* cur, hipStream_t s);
 // appends a row to every replica's observable record after a bead step, when the new step
 // count is a multiple of obs_every (no_hydro: the beads saw a fluid at rest, u = 0)
 hipError_t launch_observe(const Context& c, bool no_hydro, hipStream_t s);

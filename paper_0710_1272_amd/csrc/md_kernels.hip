@@ -1292,6 +1292,127 @@ __global__ __launch_bounds__(256) void k_observe(const Replica* __restrict__ rep
     rec[0] = cnt + 1.0;
 }
 
+// Trilinear stencil of a position: nodes floor(r_a) + {0, 1} per axis (periodic axes wrap,
+// a node beyond a free-slip face is the face node) and the 1-D weights 1 - f, f.
+__device__ __forceinline__ void trilinear_axes(const Replica& R, const double* r, int lo[3][2], double w1[3][2]) {
+    const int n[3] = {R.nx, R.ny, R.nz};
+    const int fs[3] = {R.fs[0], R.fs[1], R.fs[2]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double t = floor(r[a]);
+        if (!(t >= -1e9 && t <= 1e9)) t = 0.0;  // non-finite or absurd
+        const double fr = r[a] - t;
+        w1[a][0] = 1.0 - fr;
+        w1[a][1] = fr;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            int k = (int)t + s;
+            if (!fs[a]) {
+                k %= n[a];
+                if (k < 0) k += n[a];
+            } else {
+                k = k < 0 ? 0 : (k > n[a] - 1 ? n[a] - 1 : k);
+            }
+            lo[a][s] = k;
+        }
+    }
+}
+
+// Step 1 with the trilinear stencil, one thread per bead: u_i = sum_c w_c u(x_c) over the 8
+// surrounding nodes (u = 0 on solid ones), from the pre-collision populations; the
+// start-of-step position is kept for the spread and the bead has no single node (-1).
+template <class Real>
+__global__ __launch_bounds__(256) void k_interp_tri(const Replica* __restrict__ reps, BeadPtrs<Real> b,
+                                                    const void* cur, int storage) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= b.ntot) return;
+    const int NT = b.ntot;
+    const Replica& R = reps[b.rep_of[i]];
+    const double r[3] = {b.r[i], b.r[NT + i], b.r[2 * NT + i]};
+    int lo[3][2];
+    double w1[3][2];
+    trilinear_axes(R, r, lo, w1);
+    double u[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int g[3] = {lo[0][c & 1], lo[1][(c >> 1) & 1], lo[2][(c >> 2) & 1]};
+        if (is_solid(R, g[0], g[1], g[2])) continue;
+        const double w = w1[0][c & 1] * w1[1][(c >> 1) & 1] * w1[2][(c >> 2) & 1];
+        Real uc[3];
+        node_velocity<Real>(storage, R, cur, g, uc);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) u[a] += w * (double)uc[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        b.u[a * NT + i] = (Real)u[a];
+        b.rs[a * NT + i] = r[a];
+    }
+    b.node[i] = -1;
+}
+
+// 16-bit deviation storage: add to one element by compare-and-swap on the 32-bit word that
+// holds it (decode, add, re-encode; the other half of the word is kept as read)
+template <int S, int P>
+__device__ __forceinline__ void atomic_add_dev16(typename Codec<S>::T* addr, float val) {
+    using T = typename Codec<S>::T;
+    const uintptr_t at = (uintptr_t)addr;
+    unsigned int* word = (unsigned int*)(at & ~(uintptr_t)3);
+    const int sh = (at & 2) ? 16 : 0;
+    unsigned int old = *word, seen;
+    do {
+        seen = old;
+        const T h = __builtin_bit_cast(T, (uint16_t)((seen >> sh) & 0xffffu));
+        const T nh = Codec<S>::template store<P>(Codec<S>::template load<P>(h) + val);
+        const unsigned int nw = (seen & ~(0xffffu << sh)) | ((unsigned int)__builtin_bit_cast(uint16_t, nh) << sh);
+        old = atomicCAS(word, seen, nw);
+    } while (old != seen);
+}
+
+// Step 3 with the trilinear stencil, one thread per bead: -w_c (w_p / c_s^2) Fbar . c_p added
+// to the post-collision populations of every fluid node of the start-of-step stencil.
+// Stencils of nearby beads share nodes, so the adds are atomic (their order, and so the
+// last bits of FP32 sums, can differ between runs).
+template <int S>
+__global__ __launch_bounds__(256) void k_spread_tri(const Replica* __restrict__ reps,
+                                                    BeadPtrs<typename MDReal<S>::type> b,
+                                                    typename Codec<S>::T* __restrict__ dst, RunState* st,
+                                                    int bump_step) {
+    using C = Codec<S>;
+    using Rl = typename C::R;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (bump_step && i == 0) st->step += 1;
+    if (i >= b.ntot) return;
+    const int NT = b.ntot;
+    const Replica& R = reps[b.rep_of[i]];
+    const double r[3] = {b.rs[i], b.rs[NT + i], b.rs[2 * NT + i]};
+    const Rl F[3] = {(Rl)b.fbar[i], (Rl)b.fbar[NT + i], (Rl)b.fbar[2 * NT + i]};
+    int lo[3][2];
+    double w1[3][2];
+    trilinear_axes(R, r, lo, w1);
+    const long long V = R.V;
+    for (int c = 0; c < 8; ++c) {
+        const int g[3] = {lo[0][c & 1], lo[1][(c >> 1) & 1], lo[2][(c >> 2) & 1]};
+        if (is_solid(R, g[0], g[1], g[2])) continue;
+        const Rl w = (Rl)(w1[0][c & 1] * w1[1][(c >> 1) & 1] * w1[2][(c >> 2) & 1]);
+        typename C::T* base = dst + R.pop_base + g[0] + (long long)R.nx * (g[1] + (long long)R.ny * g[2]);
+        md_for_pops([&](auto P) {
+            constexpr int p = decltype(P)::value;
+            if constexpr (p != 0) {
+                Rl fc = 0;
+                if constexpr (cx_of(p) != 0) fc += Rl(cx_of(p)) * F[0];
+                if constexpr (cy_of(p) != 0) fc += Rl(cy_of(p)) * F[1];
+                if constexpr (cz_of(p) != 0) fc += Rl(cz_of(p)) * F[2];
+                const Rl src = -Rl(3) * w_of<Rl>(p) * fc * w;
+                if constexpr (S == LB_STORE_F32 || S == LB_STORE_F64)
+                    (void)unsafeAtomicAdd(&base[(long long)p * V], src);
+                else
+                    atomic_add_dev16<S, p>(&base[(long long)p * V], src);
+            }
+        });
+    }
+}
+
 // ---------------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------------
@@ -1424,7 +1545,41 @@ static hipError_t launch_spread_t(const Context& c, void* dst, bool bump, hipStr
     return hipGetLastError();
 }
 
+template <int S>
+static hipError_t launch_spread_tri_t(const Context& c, void* dst, bool bump, hipStream_t s) {
+    using Real = typename MDReal<S>::type;
+    const BeadPtrs<Real> b = *(const BeadPtrs<Real>*)c.bead_ptrs;
+    const int grid = (c.ntot_beads + 255) / 256;
+    hipLaunchKernelGGL((k_spread_tri<S>), dim3(grid > 0 ? grid : 1), dim3(256), 0, s, c.d_reps, b,
+                       (typename Codec<S>::T*)dst, c.d_state, bump ? 1 : 0);
+    return hipGetLastError();
+}
+
+template <class Real>
+static hipError_t launch_interp_tri_t(const Context& c, const void* cur, hipStream_t s) {
+    const BeadPtrs<Real> b = *(const BeadPtrs<Real>*)c.bead_ptrs;
+    const int grid = (c.ntot_beads + 255) / 256;
+    hipLaunchKernelGGL((k_interp_tri<Real>), dim3(grid > 0 ? grid : 1), dim3(256), 0, s, c.d_reps, b, cur,
+                       c.storage);
+    return hipGetLastError();
+}
+
+hipError_t launch_interp_trilinear(const Context& c, const void* cur, hipStream_t s) {
+    if (c.ntot_beads == 0) return hipSuccess;
+    return c.storage == LB_STORE_F64 ? launch_interp_tri_t<double>(c, cur, s)
+                                     : launch_interp_tri_t<float>(c, cur, s);
+}
+
 hipError_t launch_spread(const Context& c, void* dst, bool bump, hipStream_t s) {
+    if (c.md.stencil == LB_STENCIL_TRILINEAR) {
+        switch (c.storage) {
+            case LB_STORE_F64: return launch_spread_tri_t<LB_STORE_F64>(c, dst, bump, s);
+            case LB_STORE_F32: return launch_spread_tri_t<LB_STORE_F32>(c, dst, bump, s);
+            case LB_STORE_F16DEV: return launch_spread_tri_t<LB_STORE_F16DEV>(c, dst, bump, s);
+            case LB_STORE_BF16DEV: return launch_spread_tri_t<LB_STORE_BF16DEV>(c, dst, bump, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (c.storage) {
         case LB_STORE_F64: return launch_spread_t<LB_STORE_F64>(c, dst, bump, s);
         case LB_STORE_F32: return launch_spread_t<LB_STORE_F32>(c, dst, bump, s);

@@ -33,6 +33,7 @@ OBS_COLUMNS = ("step", "N_T", "S_H", "S_E", "K", "R_U2", "R_T2", "x_com")
 LB_ERR_BEAD_IN_SOLID, LB_ERR_BEAD_OUTSIDE, LB_ERR_NONFINITE, LB_ERR_BOND_STRETCH, LB_ERR_DENSITY = (
     1, 2, 4, 8, 16)
 LB_ERR_CONSTRAINT = 32
+LB_STENCIL_NGP, LB_STENCIL_TRILINEAR = 0, 1
 
 EXPORTED = ["lb_required_bytes", "lb_validate_config", "lb_init", "lb_step", "lb_couple", "md_step",
             "lb_moments", "lb_moments_bytes", "lb_moments_range", "lb_block_size", "lb_launch_shape", "lb_md_lanes", "lb_destroy",
@@ -57,7 +58,8 @@ class lbmd_md_params(C.Structure):
                 ("k_bond", C.c_double), ("r0", C.c_double), ("eps", C.c_double),
                 ("sigma", C.c_double), ("eps_w", C.c_double), ("sigma_w", C.c_double),
                 ("f_drive", C.c_double), ("drive_sign", C.c_int), ("rigid", C.c_int),
-                ("kappa_phi", C.c_double), ("shake_tol", C.c_double), ("shake_iter", C.c_int)]
+                ("kappa_phi", C.c_double), ("shake_tol", C.c_double), ("shake_iter", C.c_int),
+                ("stencil", C.c_int)]
 
 
 class lbmd_initial_state(C.Structure):

@@ -72,7 +72,7 @@ def test_invalid_boxes_rejected(bad):
 
 
 @pytest.mark.parametrize("bad", [dict(M=5), dict(M=0), dict(mass=0.0), dict(drive_sign=0),
-                                 dict(sigma=-1.0)])
+                                 dict(sigma=-1.0), dict(stencil=2), dict(stencil=-1)])
 def test_invalid_md_rejected(bad):
     md = MDParams(**bad)
     assert _cfg([_rep()], md).validate() == B.LB_EINVAL
