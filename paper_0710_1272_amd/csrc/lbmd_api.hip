@@ -413,8 +413,10 @@ int autotune(Context& c) {
 }
 
 // Lanes per bead of the bead kernel: times coupled-mode launches (interpolation and M
-// substeps) for every valid choice, each from the same saved bead state, then puts the
-// bead buffer and the run state back as they were.
+// substeps) for every valid choice, each from the same saved bead state and each beside a
+// lattice sweep into the spare population buffer, as in a coupled step (the sweep shares the
+// bead kernel's compute unit, which changes the best choice); then puts the bead buffer and
+// the run state back as they were.
 int autotune_md(Context& c) {
     if (c.ntot_beads == 0 || c.md_lanes != 0) return LB_OK;
     std::vector<int> cand;
@@ -446,8 +448,16 @@ int autotune_md(Context& c) {
             float ms = 1e30f;
             for (int round = 0; round < 3; ++round) {
                 if ((e = hipEventRecord(e0, c.stream)) != hipSuccess) return e;
-                for (int k = 0; k < 5; ++k)
-                    if ((e = launch_md(c, c.pops[c.cur], MD_COUPLED, c.stream)) != hipSuccess) return e;
+                for (int k = 0; k < 5; ++k) {
+                    if ((e = hipEventRecord(c.ev_fork, c.stream)) != hipSuccess) return e;
+                    if ((e = hipStreamWaitEvent(c.side, c.ev_fork, 0)) != hipSuccess) return e;
+                    if ((e = launch_md(c, c.pops[c.cur], MD_COUPLED, c.side)) != hipSuccess) return e;
+                    if ((e = hipEventRecord(c.ev_join, c.side)) != hipSuccess) return e;
+                    if ((e = launch_stream_collide(c, c.pops[c.cur], c.pops[1 - c.cur], false, c.stream)) !=
+                        hipSuccess)
+                        return e;
+                    if ((e = hipStreamWaitEvent(c.stream, c.ev_join, 0)) != hipSuccess) return e;
+                }
                 if ((e = hipEventRecord(e1, c.stream)) != hipSuccess) return e;
                 if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
                 float t = 0;
