@@ -202,6 +202,8 @@ def main(argv: Optional[List[str]] = None) -> int:
     ap.add_argument("--no-hydro", action="store_true", help="also run the no-solvent comparison")
     ap.add_argument("--seed", type=int, default=20550101)
     ap.add_argument("--obs-every", type=int, default=10)
+    ap.add_argument("--fluid-kT", type=float, default=0.0,
+                    help="temperature of the fluctuating-LB thermal source (0: none)")
     ap.add_argument("--out", default=None, help="write the JSON result here as well")
     args = ap.parse_args(argv)
 
@@ -209,11 +211,14 @@ def main(argv: Optional[List[str]] = None) -> int:
 
     storage = {"f64": WC.STORE_F64, "f32": WC.STORE_F32, "f16dev": WC.STORE_F16, "bf16dev": WC.STORE_BF16}[args.storage]
     nx, ny, nz = (int(v) for v in args.box.split(","))
-    box = WC.pore_box(nx, ny, nz)
+    import dataclasses
+
+    box = dataclasses.replace(WC.pore_box(nx, ny, nz), fluid_kT=args.fluid_kT)
     md = WC.paper_polymer() if args.model == "paper" else WC.MDParams()
     lengths = [int(v) for v in args.lengths.split(",")]
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
     result: Dict[str, object] = {"box": [nx, ny, nz], "model": args.model, "storage": args.storage,
+                                 "fluid_kT": args.fluid_kT,
                                  "events_per_length": args.events, "step_cap": args.step_cap, "lengths": {}}
     modes = [True, False] if args.no_hydro else [True]
     for hydro in modes:

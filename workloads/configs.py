@@ -187,10 +187,12 @@ ENSEMBLE_SEED_GPU = BASE_SEED + 200_000
 ENSEMBLE_STEP_CAP = 4000
 
 
-def ensemble48_n32(n_replicas: int, seed0: int, storage: int = STORE_F32) -> Workload:
+def ensemble48_n32(n_replicas: int, seed0: int, storage: int = STORE_F32,
+                   md: Optional[MDParams] = None) -> Workload:
     """n independent 48^3 boxes with one pore wall (x = 22..24) and a 32-bead chain started in
-    the pore mouth; replica k has seed seed0 + k (its chain and its random forces)."""
+    the pore mouth; replica k has seed seed0 + k (its chain and its random forces).  md:
+    the bead model (harmonic chain by default; paper_polymer() for the rigid one)."""
     box = pore_box(48, 48, 48)
     reps = [Replica(box, [32], seed0 + k) for k in range(n_replicas)]
-    return Workload(f"ensemble48_n32x{n_replicas}", reps, MDParams(), storage, ENSEMBLE_STEP_CAP,
+    return Workload(f"ensemble48_n32x{n_replicas}", reps, md or MDParams(), storage, ENSEMBLE_STEP_CAP,
                     "48^3 boxes, 3x3 pore wall, N=32 chain each, run to completion")
