@@ -196,6 +196,11 @@ int lb_validate_config(const lbmd_config* cfg) {
         total_beads += nb;
         max_beads = std::max(max_beads, nb);
     }
+    // the bead kernel keeps a replica's positions (two buffers), node and bond arrays, and
+    // for rigid chains the constraint work area, in one compute unit's LDS
+    if (max_beads > md_max_beads(cfg->md.rigid != 0))
+        return fail(LB_EINVAL, "more than " + std::to_string(md_max_beads(cfg->md.rigid != 0)) +
+                                   " beads in one replica (the bead kernel's LDS limit)");
     if (cfg->obs_every < 0 || (cfg->obs_every > 0 && (cfg->obs_capacity < 1 || cfg->obs_capacity > (1 << 24))))
         return fail(LB_EINVAL, "obs_every must be >= 0, and obs_capacity in 1..2^24 when recording");
     if (cfg->md_lanes != 0 && !md_lanes_valid(cfg->md_lanes, max_beads))

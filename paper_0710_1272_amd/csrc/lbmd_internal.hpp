@@ -123,5 +123,8 @@ hipError_t launch_interp_trilinear(const Context& c, const void* cur, hipStream_
 hipError_t launch_observe(const Context& c, bool no_hydro, hipStream_t s);
 int md_default_lanes(int max_beads);
 bool md_lanes_valid(int lanes, int max_beads);
+// most beads one replica may hold: the bead kernel's per-replica LDS arrays must fit one
+// compute unit (positions, node and bond arrays; with rigid bonds also the constraint work area)
+int md_max_beads(bool rigid);
 
 }  // namespace lbmd

@@ -1452,6 +1452,12 @@ static size_t md_lds_bytes(const Context& c, int G) {
     return b;
 }
 
+int md_max_beads(bool rigid) {
+    const size_t per = 6 * sizeof(double) + sizeof(int) + 1 + (rigid ? 15 * sizeof(double) : 0);
+    const size_t nmax = (size_t)(160 * 1024 - kMDStaticLds) / per / 64 * 64;
+    return (int)std::min<size_t>(nmax, 4096);
+}
+
 int md_default_lanes(int max_beads) {
     // lanes per bead: up to ~512 threads, so that each SIMD has two waves to interleave
     // (measured faster than one wave per SIMD for 100 beads, although the per-bead work

@@ -91,6 +91,11 @@ def test_other_invalid_configs():
     box = Box(8, 8, 8, (PERIODIC,) * 3)
     assert _cfg([Replica(box, [], 0)], with_beads=False).validate() == B.LB_OK
     assert _cfg([Replica(box, [5000], 0)]).validate() == B.LB_EINVAL
+    # the bead kernel holds a replica's positions in one compute unit's LDS: 53 bytes a bead
+    # within 158 KB allows 3008 (rounded down to 64)
+    assert _cfg([Replica(box, [3008], 0)]).validate() == B.LB_OK
+    assert _cfg([Replica(box, [3009], 0)]).validate() == B.LB_EINVAL
+    assert "LDS" in B.lib().lb_last_error_message().decode()
 
 
 def test_no_gpu_needed_for_host_calls():
