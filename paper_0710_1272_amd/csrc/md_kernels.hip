@@ -339,8 +339,12 @@ __device__ __forceinline__ void angle_forces(const double* ra, const double* rb,
 // level takes one division (the row's own new 1/b) instead of two.  Double-buffered in LDS
 // (W: [2][4][nmax] doubles: a, 1/b, c, d); one barrier per level.  Every thread of the
 // block must call it.
+// With `vote`, the barrier after the first writes also returns whether any thread passed
+// need = true in *any; without any, or with solve = false, no level runs and 0 is returned
+// (a Newton step folds its convergence test into the solve that follows it this way).
 __device__ __forceinline__ double pcr_solve(double* W, int nmax, int m, int t, double a, double b, double c,
-                                            double d) {
+                                            double d, bool vote = false, bool need = true, bool solve = true,
+                                            bool* any = nullptr) {
     const bool row = t < m;
     int buf = 0;
     double ib = 1.0 / b;
@@ -350,7 +354,13 @@ __device__ __forceinline__ double pcr_solve(double* W, int nmax, int m, int t, d
         W[(0 * 4 + 2) * nmax + t] = c;
         W[(0 * 4 + 3) * nmax + t] = d;
     }
-    __syncthreads();
+    if (vote) {
+        const bool any_need = __syncthreads_or(need) != 0;
+        *any = any_need;
+        if (!any_need || !solve) return 0.0;
+    } else {
+        __syncthreads();
+    }
     for (int s = 1; s < m; s <<= 1) {
         const double* Ws = W + buf * 4 * nmax;
         double* Wd = W + (buf ^ 1) * 4 * nmax;
@@ -960,15 +970,18 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
                     g = (double)separation_v<double, PERIODIC>(ra, rb, per, nd, sv) - md.b2;
                 }
                 const bool bad = on && !(fabs(g) <= md.shake_tol_b2);
-                if (!__syncthreads_or(bad)) break;
+                // the Jacobian is assembled before the vote, which the solve's first barrier takes
+                const double B = on ? 4.0 * im * (sv[0] * dref[0] + sv[1] * dref[1] + sv[2] * dref[2]) : 1.0;
+                const double Aa = on ? -2.0 * im * (sv[0] * dm1[0] + sv[1] * dm1[1] + sv[2] * dm1[2]) : 0.0;
+                const double Cc = on ? -2.0 * im * (sv[0] * dp1[0] + sv[1] * dp1[1] + sv[2] * dp1[2]) : 0.0;
+                bool any_bad = false;
+                const double x = pcr_solve(PCRW, nmax, m, t, Aa, B, Cc, on ? -g : 0.0, true, bad,
+                                           it < md.shake_iter, &any_bad);
+                if (!any_bad) break;
                 if (it >= md.shake_iter) {
                     flags |= LB_ERR_CONSTRAINT;
                     break;
                 }
-                const double B = on ? 4.0 * im * (sv[0] * dref[0] + sv[1] * dref[1] + sv[2] * dref[2]) : 1.0;
-                const double Aa = on ? -2.0 * im * (sv[0] * dm1[0] + sv[1] * dm1[1] + sv[2] * dm1[2]) : 0.0;
-                const double Cc = on ? -2.0 * im * (sv[0] * dp1[0] + sv[1] * dp1[1] + sv[2] * dp1[2]) : 0.0;
-                const double x = pcr_solve(PCRW, nmax, m, t, Aa, B, Cc, on ? -g : 0.0);
                 if (on) LAM[t] += x;
                 __syncthreads();
             }
