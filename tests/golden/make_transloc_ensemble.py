@@ -8,11 +8,14 @@ After every step the oracle's translocation observables are taken (Sec. III: S_H
 the radii of gyration of both sides); each event row also holds their means over the event
 (steps 1..t_done), the ratio R_T(t_done) / R_U(1), and whether the chain retracted.
 With --no-hydro the beads move alone in a fluid at rest (u = 0, no lattice, the no-solvent
-comparison of Sec. III) and the sample goes to transloc_pore48_n32_nohydro.txt.
+comparison of Sec. III) and the sample goes to transloc_pore48_n32_nohydro.txt; with
+--model paper the chain is the paper's own (rigid bonds, M = 5, eps = 2e-3) and the sample goes
+to transloc_pore48_n32_rigid.txt.
 Only oracle/ and the seeded input generators of workloads/ are called.
 
     python tests/golden/make_transloc_ensemble.py --events 256 --jobs 8
     python tests/golden/make_transloc_ensemble.py --events 512 --jobs 8 --no-hydro
+    python tests/golden/make_transloc_ensemble.py --events 256 --jobs 8 --model paper
 """
 from __future__ import annotations
 
@@ -29,8 +32,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CHUNK = 50
 
 
+def _model(name):
+    from workloads import configs as WC
+
+    return WC.paper_polymer() if name == "paper" else WC.MDParams()
+
+
 def _event(args):
-    k, hydro = args
+    k, hydro, model = args
     os.environ["OMP_NUM_THREADS"] = "1"
     import numpy as np
 
@@ -38,7 +47,7 @@ def _event(args):
     from workloads import configs as WC
     from workloads import generate as G
 
-    w = WC.ensemble48_n32(k + 1, WC.ENSEMBLE_SEED_ORACLE)
+    w = WC.ensemble48_n32(k + 1, WC.ENSEMBLE_SEED_ORACLE, md=_model(model))
     rep = w.replicas[k]
     beads = G.replica_beads(rep, w.md)
     f0 = O.equilibrium_populations(rep.box, np.full(rep.box.nodes, rep.box.rho0),
@@ -71,9 +80,14 @@ def main():
     ap.add_argument("--events", type=int, default=256)
     ap.add_argument("--jobs", type=int, default=8)
     ap.add_argument("--no-hydro", action="store_true")
+    ap.add_argument("--model", choices=["harmonic", "paper"], default="harmonic")
     args = ap.parse_args()
     hydro = not args.no_hydro
-    out = os.path.join(HERE, "transloc_pore48_n32.txt" if hydro else "transloc_pore48_n32_nohydro.txt")
+    if args.model == "paper":
+        assert hydro, "the rigid-chain sample is the coupled one"
+        out = os.path.join(HERE, "transloc_pore48_n32_rigid.txt")
+    else:
+        out = os.path.join(HERE, "transloc_pore48_n32.txt" if hydro else "transloc_pore48_n32_nohydro.txt")
     from multiprocessing import get_context
 
     from workloads import configs as WC
@@ -81,12 +95,12 @@ def main():
     t0 = time.time()
     rows = []
     with get_context("spawn").Pool(args.jobs) as pool:
-        for i, row in enumerate(pool.imap(_event, [(k, hydro) for k in range(args.events)])):
+        for i, row in enumerate(pool.imap(_event, [(k, hydro, args.model) for k in range(args.events)])):
             rows.append(row)
             print(f"event {i}: seed {row[0]} t_done {row[1]} flags {row[2]} S_H {row[3]:.3e} "
                   f"S_E {row[4]:.3e} K {row[5]:.3e} R_T/R_U {row[6]:.3f} retracted {row[7]} "
                   f"({time.time() - t0:.0f} s)", flush=True)
-    md = WC.MDParams()
+    md = _model(args.model)
     with open(out, "w") as fh:
         fh.write("# Translocation times of the FP64 oracle (coupled LB + bead steps, Sec. II-III).\n"
                  if hydro else
@@ -98,7 +112,7 @@ def main():
                  "one chain of 32 beads from the pore mouth\n")
         fh.write(f"# M={md.M} mass={md.mass} gamma={md.gamma} kT={md.kT} k_bond={md.k_bond} "
                  f"r0={md.r0} eps={md.eps} sigma={md.sigma} eps_w={md.eps_w} sigma_w={md.sigma_w} "
-                 f"f_drive={md.f_drive}\n")
+                 f"f_drive={md.f_drive} rigid={md.rigid} kappa_phi={md.kappa_phi}\n")
         fh.write(f"# seeds {WC.ENSEMBLE_SEED_ORACLE}+k; step cap {WC.ENSEMBLE_STEP_CAP}; "
                  "t_done = -1 marks a censored event\n")
         fh.write("# per event: means over steps 1..t_done of S_H = m gamma sum v.u, S_E = sum "

@@ -27,6 +27,7 @@ from workloads import generate as G
 HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 GOLDEN = os.path.join(HERE, "transloc_pore48_n32.txt")
 GOLDEN_NO_HYDRO = os.path.join(HERE, "transloc_pore48_n32_nohydro.txt")
+GOLDEN_RIGID = os.path.join(HERE, "transloc_pore48_n32_rigid.txt")
 N_GPU = 512
 CHECK_EVERY = 250
 
@@ -45,7 +46,7 @@ def oracle_times(path=GOLDEN) -> np.ndarray:
     return oracle_rows(path)[:, 1].astype(np.int64)
 
 
-@pytest.mark.parametrize("path", [GOLDEN, GOLDEN_NO_HYDRO], ids=["coupled", "nohydro"])
+@pytest.mark.parametrize("path", [GOLDEN, GOLDEN_NO_HYDRO, GOLDEN_RIGID], ids=["coupled", "nohydro", "rigid"])
 def test_oracle_ensemble_file(path):
     """The stored sample is complete, uncensored and drawn from the oracle seed range."""
     rows = np.loadtxt(path, comments="#", ndmin=2)
@@ -66,14 +67,17 @@ def test_solvent_speeds_translocation():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("storage,hydro", [(WC.STORE_F64, True), (WC.STORE_F32, True), (WC.STORE_F16, True),
-                                           (WC.STORE_BF16, True), (WC.STORE_F32, False)],
-                         ids=["f64", "f32", "f16dev", "bf16dev", "nohydro"])
-def test_translocation_time_distribution(storage, hydro):
+@pytest.mark.parametrize("storage,hydro,model", [(WC.STORE_F64, True, "harmonic"), (WC.STORE_F32, True, "harmonic"),
+                                                 (WC.STORE_F16, True, "harmonic"), (WC.STORE_BF16, True, "harmonic"),
+                                                 (WC.STORE_F32, False, "harmonic"), (WC.STORE_F32, True, "paper")],
+                         ids=["f64", "f32", "f16dev", "bf16dev", "nohydro", "rigid"])
+def test_translocation_time_distribution(storage, hydro, model):
     from scipy import stats
 
-    t_ora = oracle_times(GOLDEN if hydro else GOLDEN_NO_HYDRO)
-    w = WC.ensemble48_n32(N_GPU, WC.ENSEMBLE_SEED_GPU, storage)
+    golden = GOLDEN_RIGID if model == "paper" else (GOLDEN if hydro else GOLDEN_NO_HYDRO)
+    t_ora = oracle_times(golden)
+    md = WC.paper_polymer() if model == "paper" else WC.MDParams()
+    w = WC.ensemble48_n32(N_GPU, WC.ENSEMBLE_SEED_GPU, storage, md=md)
     log(f"ensemble {w.name} storage {WC.STORE_NAMES[storage]}{'' if hydro else ' without solvent'}: "
         f"{N_GPU} replicas, cap {WC.ENSEMBLE_STEP_CAP} steps")
     beads = np.concatenate(G.workload_beads(w))
@@ -106,7 +110,7 @@ def test_translocation_time_distribution(storage, hydro):
 
     # per-event observables of the Sec. III analysis
     from paper_0710_1272_amd import ensemble as E
-    ora = oracle_rows(GOLDEN if hydro else GOLDEN_NO_HYDRO)
+    ora = oracle_rows(golden)
     gpu = {k: [] for k in OBS_COLS}
     for rows, t in zip(records, t_gpu):
         ev = E.event_rows(rows, int(t))
