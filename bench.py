@@ -213,11 +213,32 @@ def extra_workloads(steps_scale=1.0):
     n = int(60 * steps_scale)
     dt = time_steps(sim, n, diag_every=30)
     rl = lattice_roofline(sim, w.fluid_nodes, WC.STORE_F16, n=16)
-    out[f"{w.name}:f16dev"] = {"replica_steps_per_s": round(len(w.replicas) * n / dt, 1),
+    batched = len(w.replicas) * n / dt
+    out[f"{w.name}:f16dev"] = {"replica_steps_per_s": round(batched, 1),
                                "mlups": round(w.fluid_nodes * n / dt / 1e6, 1),
                                "ms_per_step": round(dt / n * 1e3, 4), "lattice": rl,
                                "launch": sim.launch_shape()}
     sim.close()
+    torch.cuda.empty_cache()
+    # the plain form for comparison: replicas one at a time in FP32; the mean step time of 8
+    # replicas at evenly spaced size ranks estimates that of the whole batch
+    import numpy as np
+
+    order = np.argsort([r.box.nodes * 1000 + r.n_beads for r in w.replicas])
+    picks = [int(order[round(k * (len(order) - 1) / 7)]) for k in range(8)]
+    times = []
+    for k in picks:
+        one = dataclasses.replace(w, replicas=[w.replicas[k]])
+        s1 = build_case(one, WC.STORE_F32)
+        s1.step(20)
+        n1 = int(200 * steps_scale)
+        times.append(time_steps(s1, n1, diag_every=n1) / n1)
+        s1.close()
+    seq = 1.0 / float(np.mean(times))
+    out[f"{w.name}:f16dev"]["single_f32_replica_steps_per_s"] = round(seq, 1)
+    out[f"{w.name}:f16dev"]["speedup_vs_single_f32"] = round(batched / seq, 2)
+    out[f"{w.name}:f16dev"]["single_f32_sample"] = ("8 replicas at evenly spaced size ranks, each alone in "
+                                                    "FP32 storage (autotuned, graph-launched)")
     torch.cuda.empty_cache()
 
     w = WC.c5_large(WC.STORE_F32)
