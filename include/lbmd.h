@@ -155,9 +155,13 @@ typedef struct lbmd_config {
 } lbmd_config;
 
 /* lattice_mapping */
-#define LB_MAP_AUTO 0  /* flat (LB_CFG_AUTOTUNE also tries rows) */
+#define LB_MAP_AUTO 0  /* flat (LB_CFG_AUTOTUNE also tries rows and shifted) */
 #define LB_MAP_FLAT 1  /* each wave takes 64 consecutive nodes of a replica */
 #define LB_MAP_ROWS 2  /* each wave takes one segment of at most 64 nodes of one x-row */
+#define LB_MAP_SHIFTED 3 /* flat, with each x-row rotated by whole 128-byte lines so that
+                            the planes within one node of a wall share as few waves as
+                            possible (the other waves skip the bounce-back tests); the same
+                            as flat unless nx is a multiple of 64 and the replica has walls */
 /* xcd_order (a value C > 0 deals chunks of C consecutive tiles round-robin to the XCDs) */
 #define LB_XCD_AUTO 0        /* contiguous for one replica, hardware order for several */
 #define LB_XCD_HARDWARE (-1) /* blocks in launch order (the hardware deals them round-robin) */
@@ -272,7 +276,7 @@ int lb_moments_range(lbmd_ctx* ctx, int replica, unsigned what, long long node0,
 /* Lattice-kernel launch shape in use (threads per block). */
 int lb_block_size(const lbmd_ctx* ctx);
 
-/* Lattice-kernel launch shape in use: threads per block, LB_MAP_FLAT/ROWS, the XCD
+/* Lattice-kernel launch shape in use: threads per block, LB_MAP_FLAT/ROWS/SHIFTED, the XCD
  * tile order (LB_XCD_HARDWARE, LB_XCD_CONTIGUOUS or a chunk size) and whether the
  * populations are written with non-temporal stores (1: both buffers together exceed
  * 160 MB, so they are streamed past the last-level cache; 0: they stay cached between

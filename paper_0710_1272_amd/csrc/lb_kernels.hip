@@ -307,8 +307,12 @@ __device__ __forceinline__ void add_thermal(Rl* f, uint32_t node, uint32_t step,
     });
 }
 
-// Thread-to-node mappings of the lattice kernel.
-enum LatticeMapping { MAP_FLAT = 0, MAP_ROWS = 1 };
+// Thread-to-node mappings of the lattice kernel.  MAP_SHIFTED is MAP_FLAT with every
+// x-row rotated by the replica's x_shift, chosen on the host so that the planes within one
+// node of a wall fall into as few 64-lane waves as possible: the other waves of a row then
+// take the interior gather (used when nx is a multiple of 64, so that waves are row
+// segments).
+enum LatticeMapping { MAP_FLAT = 0, MAP_ROWS = 1, MAP_SHIFTED = 2 };
 
 template <int S, int BLOCK, bool NT, bool TH>
 __global__ __launch_bounds__(BLOCK) void k_stream_collide(const Replica* __restrict__ reps,
@@ -348,10 +352,15 @@ __global__ __launch_bounds__(BLOCK) void k_stream_collide(const Replica* __restr
     } else {
         // 64 consecutive nodes per wave; waves that touch a y/z face take the general
         // resolver, waves next to a wall the solid-testing one
-        idx = (tile - prefix[r]) * BLOCK + threadIdx.x;
-        bool active = idx < R.V;
-        const uint32_t t = fdiv((uint32_t)idx, R.div_nx);
-        const int x = idx - (int)t * R.nx;
+        const int n = (tile - prefix[r]) * BLOCK + threadIdx.x;
+        bool active = n < R.V;
+        const uint32_t t = fdiv((uint32_t)n, R.div_nx);
+        int x = n - (int)t * R.nx;
+        if (mapping == MAP_SHIFTED) {
+            x += R.x_shift;
+            if (x >= R.nx) x -= R.nx;
+        }
+        idx = x + (int)t * R.nx;
         const uint32_t zz = fdiv(t, R.div_ny);
         const int y = (int)t - (int)zz * R.ny;
         const int z = (int)zz;

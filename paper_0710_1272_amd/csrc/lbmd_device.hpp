@@ -163,6 +163,7 @@ struct Replica {
     int n_walls;
     int wall[LB_MAX_WALLS][6];
     int wzone_lo, wzone_hi;  // x range within one node of any wall (lanes that need solid checks)
+    int x_shift;        // shifted flat mapping: position n of a row holds x = (n + x_shift) mod nx
     long long pop_base; // element offset of this replica's [19][V] block
     int bead0, n_beads;
     uint32_t seed_lo, seed_hi;

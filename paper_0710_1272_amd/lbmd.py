@@ -21,7 +21,7 @@ LB_BC_PERIODIC, LB_BC_FREESLIP = 0, 1
 LB_STORE_F64, LB_STORE_F32, LB_STORE_F16DEV, LB_STORE_BF16DEV = 0, 1, 2, 3
 LB_MAX_WALLS = 2
 LB_CFG_NO_GRAPH, LB_CFG_AUTOTUNE = 1, 2
-LB_MAP_AUTO, LB_MAP_FLAT, LB_MAP_ROWS = 0, 1, 2
+LB_MAP_AUTO, LB_MAP_FLAT, LB_MAP_ROWS, LB_MAP_SHIFTED = 0, 1, 2, 3
 LB_XCD_AUTO, LB_XCD_HARDWARE, LB_XCD_CONTIGUOUS = 0, -1, -2
 LB_BUF_POPS, LB_BUF_BEADS, LB_BUF_WORK = 0, 1, 2
 LB_STEP_COUPLED, LB_STEP_NO_HYDRO = 1, 2
@@ -254,7 +254,8 @@ class Simulation:
         b, m, x, nt = C.c_int(), C.c_int(), C.c_int(), C.c_int()
         _check(lib().lb_launch_shape(self.ctx, C.byref(b), C.byref(m), C.byref(x), C.byref(nt)),
                "lb_launch_shape")
-        return {"block": b.value, "mapping": {LB_MAP_FLAT: "flat", LB_MAP_ROWS: "rows"}[m.value],
+        names = {LB_MAP_FLAT: "flat", LB_MAP_ROWS: "rows", LB_MAP_SHIFTED: "shifted"}
+        return {"block": b.value, "mapping": names[m.value],
                 "xcd_order": x.value, "nt_stores": bool(nt.value), "md_lanes": self.md_lanes}
 
     @property

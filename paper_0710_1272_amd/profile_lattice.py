@@ -51,7 +51,8 @@ def run(args):
 
     w, st = workload(args.workload, args.storage)
     reps = [WC.Replica(r.box, [], r.seed) for r in w.replicas]
-    sim = B.Simulation(reps, w.md, st, {})
+    mapping = {"flat": B.LB_MAP_FLAT, "rows": B.LB_MAP_ROWS, "shifted": B.LB_MAP_SHIFTED}[args.mapping]
+    sim = B.Simulation(reps, w.md, st, {}, mapping=mapping)
     for _ in range(LAUNCHES):
         sim.step(1, coupled=False)
     torch.cuda.synchronize()
@@ -95,7 +96,8 @@ def summarize(args):
     entry = {"bytes_per_launch": round(fetch + write), "fetch_bytes": round(fetch),
              "write_bytes": round(write), "alg_bytes": 2 * alg, "fetch_over_alg": round(fetch / alg, 4),
              "write_over_alg": round(write / alg, 4), "fetch_scale": round(sf, 4),
-             "write_scale": round(sw, 4), "launches": len(lat_f), "kernel_hash": kernel_source_hash()}
+             "write_scale": round(sw, 4), "launches": len(lat_f), "mapping": args.mapping,
+             "kernel_hash": kernel_source_hash()}
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -113,6 +115,9 @@ def main():
     ap.add_argument("mode", choices=["run", "summarize"])
     ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c5"])
     ap.add_argument("--storage", default="f32", choices=["f32", "f16dev", "bf16dev"])
+    ap.add_argument("--mapping", default="shifted", choices=["flat", "rows", "shifted"],
+                    help="thread-to-node mapping of the lattice launches (shifted is flat where "
+                         "no row rotation applies)")
     ap.add_argument("--fetch-csv")
     ap.add_argument("--write-csv")
     args = ap.parse_args()

@@ -88,6 +88,9 @@ def test_other_invalid_configs():
     assert _cfg([_rep()], storage=7).validate() == B.LB_EINVAL
     assert _cfg([_rep()], with_beads=False).validate() == B.LB_EINVAL  # beads need positions
     assert _cfg([_rep()], block_size=96).validate() == B.LB_EINVAL
+    assert _cfg([_rep()], mapping=B.LB_MAP_SHIFTED).validate() == B.LB_OK
+    assert _cfg([_rep()], mapping=B.LB_MAP_SHIFTED + 1).validate() == B.LB_EINVAL
+    assert _cfg([_rep()], mapping=-1).validate() == B.LB_EINVAL
     box = Box(8, 8, 8, (PERIODIC,) * 3)
     assert _cfg([Replica(box, [], 0)], with_beads=False).validate() == B.LB_OK
     assert _cfg([Replica(box, [5000], 0)]).validate() == B.LB_EINVAL

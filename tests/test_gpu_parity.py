@@ -56,19 +56,41 @@ BOXES = [
 ]
 
 
+MAPPINGS = {"flat": 1, "rows": 2, "shifted": 3}  # LB_MAP_FLAT, LB_MAP_ROWS, LB_MAP_SHIFTED
+
+
+@pytest.mark.parametrize("mapping", list(MAPPINGS))
 @pytest.mark.parametrize("block", [64, 256, 1024])
 @pytest.mark.parametrize("bi", range(len(BOXES)))
-def test_boundaries_fp64(bi, block):
+def test_boundaries_fp64(bi, block, mapping):
     box = BOXES[bi]
     rep = Replica(box, [], 3)
     rho, u = G.random_small_flow(box, seed=bi)
-    log(f"boundaries fp64 box={bi} block={block}")
+    log(f"boundaries fp64 box={bi} block={block} mapping={mapping}")
     ora = oracle_sim(rep, MDParams(), rho, u)
     ora.step(30, coupled=False)
-    with gpu_sim([rep], MDParams(), F64, rho, u, block_size=block) as sim:
+    with gpu_sim([rep], MDParams(), F64, rho, u, block_size=block, mapping=MAPPINGS[mapping]) as sim:
+        assert sim.launch_shape()["mapping"] == mapping
         sim.step(30, coupled=False)
         f = sim.populations()
     assert max_rel(f, ora.f, _fluid(box)) < 1e-12
+
+
+@pytest.mark.parametrize("storage", [F32, F16])
+def test_mappings_identical(storage):
+    """Every thread-to-node mapping computes each node the same way: bit-identical
+    populations after 20 steps of the 128 x 64 x 64 pore box."""
+    w = WC.c2_translocation(storage)
+    rep = Replica(w.replicas[0].box, [], w.replicas[0].seed)
+    rho, u = G.random_small_flow(rep.box, seed=5, du=0.02)
+    out = {}
+    for name, m in MAPPINGS.items():
+        log(f"mappings identical {WC.STORE_NAMES[storage]} mapping={name}")
+        with gpu_sim([rep], w.md, storage, rho, u, mapping=m) as sim:
+            sim.step(20, coupled=False)
+            out[name] = sim.populations()
+    assert np.array_equal(out["rows"], out["flat"])
+    assert np.array_equal(out["shifted"], out["flat"])
 
 
 def test_init_populations_roundtrip():
