@@ -2,7 +2,7 @@
 (autotuned launch shapes, HIP graphs of coupled steps).
 
 * 128x64x64 / N=100 (FP32): 30 coupled steps in one call, every population and bead
-  against the oracle.
+  against the oracle (lattice shape autotuned, 4 lanes per bead).
 * 256x128x128 / N=400: 10 coupled steps, FP32 pointwise and FP16-deviation storage
   against the oracle's velocity field.
 * 256 batched replicas (cubic 48..96, N in [20, 400]): 5 coupled steps of the whole
@@ -49,7 +49,10 @@ def test_c2_bench_configuration_30_steps():
     for _ in range(30):
         ora.step(1)
         margin = min(margin, min_tie_distance(ora.r))
-    with gpu_sim([rep], w.md, F32, beads=beads, flags=_autotune()) as sim:
+    # the lattice launch shape is autotuned as in the benchmark (every shape gives the same
+    # bits); the lanes per bead are held at the 4 the benchmark's tuner picks for this
+    # workload, since they set the order of the bead-force sums and so the exact drift
+    with gpu_sim([rep], w.md, F32, beads=beads, flags=_autotune(), md_lanes=4) as sim:
         log(f"  launch shape {sim.launch_shape()}")
         sim.step(30)
         f = sim.populations()
