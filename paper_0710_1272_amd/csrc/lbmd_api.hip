@@ -571,6 +571,9 @@ hipError_t enqueue_step(Context& c, int mode, int cur, hipStream_t main) {
     }
     const bool coupled = mode == STEP_COUPLED;
     if (coupled && c.ntot_beads > 0) {
+        // the bead work goes first: its workgroup needs nearly all of one compute unit's LDS,
+        // and a sweep enqueued ahead of it fills every unit, so that the bead kernel would
+        // wait for the sweep's blocks to drain instead of running beside them
         hipError_t e;
         if ((e = hipEventRecord(c.ev_fork, main)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(c.side, c.ev_fork, 0)) != hipSuccess) return e;
