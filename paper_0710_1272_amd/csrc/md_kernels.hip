@@ -1177,7 +1177,7 @@ __global__ __launch_bounds__(256) void k_spread(const Replica* __restrict__ reps
                                                 int bump_step) {
     using C = Codec<S>;
     using Rl = typename C::R;
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (bump_step && i == 0) st->step += 1;
     if (i >= b.ntot) return;
     // one round trip for everything a leader needs: where, stride, force
@@ -1558,8 +1558,11 @@ template <int S>
 static hipError_t launch_spread_t(const Context& c, void* dst, bool bump, hipStream_t s) {
     using Real = typename MDReal<S>::type;
     const BeadPtrs<Real> b = *(const BeadPtrs<Real>*)c.bead_ptrs;
-    const int grid = (c.ntot_beads + 255) / 256;
-    hipLaunchKernelGGL((k_spread<S>), dim3(grid > 0 ? grid : 1), dim3(256), 0, s, c.d_reps, b,
+    // 64 threads a block: each leader's 18 read-modify-writes miss the caches when the
+    // sweep streamed the populations past them, and more compute units keep more of
+    // these misses in flight
+    const int grid = (c.ntot_beads + 63) / 64;
+    hipLaunchKernelGGL((k_spread<S>), dim3(grid > 0 ? grid : 1), dim3(64), 0, s, c.d_reps, b,
                        (typename Codec<S>::T*)dst, c.d_state, bump ? 1 : 0);
     return hipGetLastError();
 }
