@@ -1337,7 +1337,7 @@ __device__ __forceinline__ void trilinear_axes(const Replica& R, const double* r
 template <class Real>
 __global__ __launch_bounds__(256) void k_interp_tri(const Replica* __restrict__ reps, BeadPtrs<Real> b,
                                                     const void* cur, int storage) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= b.ntot) return;
     const int NT = b.ntot;
     const Replica& R = reps[b.rep_of[i]];
@@ -1393,7 +1393,7 @@ __global__ __launch_bounds__(256) void k_spread_tri(const Replica* __restrict__ 
                                                     int bump_step) {
     using C = Codec<S>;
     using Rl = typename C::R;
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (bump_step && i == 0) st->step += 1;
     if (i >= b.ntot) return;
     const int NT = b.ntot;
@@ -1571,8 +1571,9 @@ template <int S>
 static hipError_t launch_spread_tri_t(const Context& c, void* dst, bool bump, hipStream_t s) {
     using Real = typename MDReal<S>::type;
     const BeadPtrs<Real> b = *(const BeadPtrs<Real>*)c.bead_ptrs;
-    const int grid = (c.ntot_beads + 255) / 256;
-    hipLaunchKernelGGL((k_spread_tri<S>), dim3(grid > 0 ? grid : 1), dim3(256), 0, s, c.d_reps, b,
+    // 64 threads a block, as for the nearest-node spread
+    const int grid = (c.ntot_beads + 63) / 64;
+    hipLaunchKernelGGL((k_spread_tri<S>), dim3(grid > 0 ? grid : 1), dim3(64), 0, s, c.d_reps, b,
                        (typename Codec<S>::T*)dst, c.d_state, bump ? 1 : 0);
     return hipGetLastError();
 }
@@ -1580,8 +1581,10 @@ static hipError_t launch_spread_tri_t(const Context& c, void* dst, bool bump, hi
 template <class Real>
 static hipError_t launch_interp_tri_t(const Context& c, const void* cur, hipStream_t s) {
     const BeadPtrs<Real> b = *(const BeadPtrs<Real>*)c.bead_ptrs;
-    const int grid = (c.ntot_beads + 255) / 256;
-    hipLaunchKernelGGL((k_interp_tri<Real>), dim3(grid > 0 ? grid : 1), dim3(256), 0, s, c.d_reps, b, cur,
+    // 64 threads a block: each bead's 8 x 19 population reads may miss the caches, and
+    // more compute units keep more misses in flight
+    const int grid = (c.ntot_beads + 63) / 64;
+    hipLaunchKernelGGL((k_interp_tri<Real>), dim3(grid > 0 ? grid : 1), dim3(64), 0, s, c.d_reps, b, cur,
                        c.storage);
     return hipGetLastError();
 }
