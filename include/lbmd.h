@@ -134,6 +134,18 @@ typedef struct lbmd_initial_state {
 #define LB_CFG_AUTOTUNE 2u   /* time candidate launch shapes (lattice kernel, lanes per bead of
                                 the bead kernel) at lb_init and keep the fastest; the bead
                                 state is restored after the trial steps */
+#define LB_CFG_DETERMINISTIC 4u /* bitwise identical results from run to run for one configuration.
+                                   The nearest-node path always is: one leader bead per node adds
+                                   the summed reaction of the node's beads in bead order.  With it,
+                                   the trilinear spread (step 3 of Sec. II) rounds each contribution
+                                   -w_c (w_p / c_s^2) Fbar . c_p once to a multiple of 2^-48, sums a
+                                   node's contributions as 64-bit integers (exact, so in any order)
+                                   and adds each node's sums to its populations once, instead of
+                                   floating-point atomic adds whose order varies; and LB_CFG_AUTOTUNE
+                                   leaves the lanes per bead at their choice by bead count, since
+                                   they set the order of the bead-force sums.  The lattice kernel's
+                                   launch shape never changes results.  A contribution above 16384
+                                   in magnitude is dropped and sets LB_ERR_NONFINITE */
 
 typedef struct lbmd_config {
     int n_replicas;
@@ -224,6 +236,13 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
  * counter advances as for any step.  Asynchronous: returns launch errors, or
  * LB_EINVAL for both flags together. */
 int lb_step(lbmd_ctx* ctx, int n_steps, unsigned flags);
+
+/* Captures and instantiates, for either population-buffer parity, the HIP graphs that
+ * lb_step(ctx, n_steps, flags) launches (graphs of 16 steps and one of n_steps mod 16), so
+ * that later lb_step calls of that length capture and instantiate nothing.  Enqueues no work
+ * and leaves the state unchanged; does nothing with LB_CFG_NO_GRAPH.  Returns LB_EINVAL for
+ * n_steps < 0 or both step flags, LB_EDEVICE if a capture fails. */
+int lb_graph_prepare(lbmd_ctx* ctx, int n_steps, unsigned flags);
 
 #define LB_COUPLE_INTERP 1u /* step 1 of Sec. II alone: u(x) -> u_i, nearest node of each bead */
 #define LB_COUPLE_SPREAD 2u /* step 3 alone: add the spread reaction of the last MD call's Fbar */

@@ -102,7 +102,7 @@ WorkLayout work_layout(int n_reps, int max_V, long long max_stage_nodes) {
     return L;
 }
 
-BeadLayout bead_layout(int ntot, int n_reps, size_t rs, int obs_rows) {
+BeadLayout bead_layout(int ntot, int n_reps, size_t rs, int obs_rows, bool trilinear) {
     BeadLayout L{};
     size_t off = 0;
     const size_t N = (size_t)std::max(ntot, 1);
@@ -121,6 +121,16 @@ BeadLayout bead_layout(int ntot, int n_reps, size_t rs, int obs_rows) {
     L.rref = off;     off += align256(3 * N * sizeof(double));
     L.rs = off;       off += align256(3 * N * sizeof(double));
     L.obs = off;      off += align256((size_t)std::max(n_reps, 1) * (size_t)obs_rows * 8 * sizeof(double));
+    // a bead's stencil touches at most 8 nodes: a table of at least 16 slots a bead stays at
+    // most half full
+    L.hcap = 0;
+    if (trilinear) {
+        L.hcap = 64;
+        while (L.hcap < 16 * N) L.hcap <<= 1;
+    }
+    L.hkey = off;     off += align256((size_t)L.hcap * sizeof(unsigned long long));
+    L.hV = off;       off += align256((size_t)L.hcap * sizeof(int));
+    L.hsum = off;     off += align256((size_t)18 * L.hcap * sizeof(long long));
     L.total = off;
     return L;
 }
@@ -238,7 +248,9 @@ size_t lb_required_bytes(const lbmd_config* cfg, int which) {
     switch (which) {
         case LB_BUF_POPS: return align256((size_t)19 * (size_t)t.nodes * store_size(cfg->storage));
         case LB_BUF_BEADS:
-            return bead_layout(t.beads, cfg->n_replicas, real_size(cfg->storage), obs_rows(cfg)).total;
+            return bead_layout(t.beads, cfg->n_replicas, real_size(cfg->storage), obs_rows(cfg),
+                               t.beads > 0 && cfg->md.stencil == LB_STENCIL_TRILINEAR)
+                .total;
         case LB_BUF_WORK: return work_layout(cfg->n_replicas, t.max_V, kStageNodes).total;
         default: g_last_error = "unknown buffer id"; return 0;
     }
@@ -294,7 +306,8 @@ int set_lattice_shape(Context& c, int block, int mapping = -1) {
 template <class Real>
 int setup_beads(Context& c, const lbmd_config* cfg) {
     const BeadLayout L = bead_layout(c.ntot_beads, (int)c.reps.size(), sizeof(Real),
-                                     c.obs_every > 0 ? c.obs_capacity + 1 : 0);
+                                     c.obs_every > 0 ? c.obs_capacity + 1 : 0,
+                                     c.ntot_beads > 0 && c.md.stencil == LB_STENCIL_TRILINEAR);
     char* base = (char*)c.beads;
     BeadPtrs<Real>* p = new (std::nothrow) BeadPtrs<Real>;
     if (!p) return fail(LB_ENOMEM, "host allocation");
@@ -313,6 +326,10 @@ int setup_beads(Context& c, const lbmd_config* cfg) {
     p->rref = (double*)(base + L.rref);
     p->rs = (double*)(base + L.rs);
     p->obs = (double*)(base + L.obs);
+    p->hkey = (unsigned long long*)(base + L.hkey);
+    p->hV = (int*)(base + L.hV);
+    p->hsum = (long long*)(base + L.hsum);
+    p->hcap = L.hcap;
     p->obs_every = c.obs_every;
     p->obs_cap = c.obs_capacity;
     p->ntot = c.ntot_beads;
@@ -357,6 +374,11 @@ int setup_beads(Context& c, const lbmd_config* cfg) {
         HIP_TRY(hipMemcpy(p->rep_of, rep_of.data(), N * sizeof(int), hipMemcpyHostToDevice));
     }
     HIP_TRY(hipMemcpy(p->diag, diag.data(), 8 * c.reps.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (L.hcap > 0) {
+        // the table starts empty; the spread leaves it empty after every step
+        HIP_TRY(hipMemset(p->hkey, 0, (size_t)L.hcap * sizeof(unsigned long long)));
+        HIP_TRY(hipMemset(p->hsum, 0, (size_t)18 * L.hcap * sizeof(long long)));
+    }
     if (c.obs_every > 0) {
         // header rows (rows recorded, every, capacity); the rows themselves start unset (step -1)
         const size_t rows = (size_t)c.obs_capacity + 1;
@@ -465,8 +487,9 @@ int autotune_md(Context& c) {
         if (md_lanes_valid(G, c.max_beads)) cand.push_back(G);
     if (cand.size() < 2) return LB_OK;
     const size_t real = c.storage == LB_STORE_F64 ? sizeof(double) : sizeof(float);
-    const size_t bytes =
-        bead_layout(c.ntot_beads, (int)c.reps.size(), real, c.obs_every > 0 ? c.obs_capacity + 1 : 0).total;
+    const size_t bytes = bead_layout(c.ntot_beads, (int)c.reps.size(), real, c.obs_every > 0 ? c.obs_capacity + 1 : 0,
+                                     c.md.stencil == LB_STENCIL_TRILINEAR)
+                             .total;
     void* save = nullptr;
     HIP_TRY(hipMalloc(&save, bytes + sizeof(RunState)));
     RunState* save_st = (RunState*)((char*)save + bytes);
@@ -648,6 +671,7 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
     c.md_params = cfg->md;
     c.stream = (hipStream_t)hip_stream;
     c.use_graph = !(cfg->flags & LB_CFG_NO_GRAPH);
+    c.deterministic = (cfg->flags & LB_CFG_DETERMINISTIC) != 0;
 
     const Totals t = totals(cfg);
     c.total_nodes = t.nodes;
@@ -731,6 +755,9 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
     const double skin = 1.0;
     md.rl2 = (std::sqrt(md.rc2) + skin + 1e-3) * (std::sqrt(md.rc2) + skin + 1e-3);
     md.half_skin2 = 0.25 * skin * skin;
+    // two beads on one node are at most sqrt(3) apart (the node's unit cell); a kept list
+    // holds every non-bonded pair closer than rc, so it names them only when rc covers that
+    md.node_scan_all = std::sqrt(md.rc2) < std::sqrt(3.0) + 1e-3 ? 1 : 0;
     md.f_drive = m.drive_sign * m.f_drive;
     md.rigid = m.rigid;
     md.shake_iter = m.shake_iter;
@@ -852,7 +879,9 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
     }
     if (cfg->flags & LB_CFG_AUTOTUNE) {
         if ((rc = autotune(c))) return bail(rc);
-        if ((rc = autotune_md(c))) return bail(rc);
+        // the lanes per bead set the order of the bead-force sums: a deterministic context
+        // keeps the choice by bead count (or the configured one) rather than a timed one
+        if (!c.deterministic && (rc = autotune_md(c))) return bail(rc);
     }
     if ((rc = check(hipStreamSynchronize(c.stream), "sync"))) return bail(rc);
     *out = ctx;
@@ -888,6 +917,30 @@ int lb_step(lbmd_ctx* ctx, int n_steps, unsigned flags) {
         if (flips) c.cur = 1 - c.cur;
     }
     c.host_step += n_steps;
+    return LB_OK;
+}
+
+int lb_graph_prepare(lbmd_ctx* ctx, int n_steps, unsigned flags) {
+    if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+    if (n_steps < 0) return fail(LB_EINVAL, "n_steps < 0");
+    if ((flags & LB_STEP_COUPLED) && (flags & LB_STEP_NO_HYDRO))
+        return fail(LB_EINVAL, "LB_STEP_COUPLED and LB_STEP_NO_HYDRO exclude each other");
+    Context& c = ctx->c;
+    if (!c.use_graph || n_steps == 0) return LB_OK;
+    const int mode = (flags & LB_STEP_COUPLED) ? STEP_COUPLED : (flags & LB_STEP_NO_HYDRO) ? STEP_NO_HYDRO : STEP_LB;
+    // lb_step launches graphs of kGraphSteps steps and one of the remainder, starting from
+    // either buffer parity
+    const int lens[2] = {n_steps >= Context::kGraphSteps ? (int)Context::kGraphSteps : 0,
+                         n_steps % Context::kGraphSteps};
+    for (int parity = 0; parity < 2; ++parity)
+        for (int len : lens) {
+            if (len == 0) continue;
+            hipGraphExec_t& g = c.graphs[mode][parity][len];
+            if (!g) {
+                const int rc = build_graph(c, mode, parity, len, &g);
+                if (rc) return rc;
+            }
+        }
     return LB_OK;
 }
 

@@ -353,6 +353,11 @@ struct BeadPtrs {
                         // LB steps while diag[7] of the replica is 1)
     double* rs;         // [3][Ntot] start-of-step positions (trilinear stencil of the spread)
     double* obs;        // [n_replicas][obs_cap + 1][8] observable record (header row first)
+    // deterministic trilinear spread: open-addressing table of the nodes the stencils touch
+    unsigned long long* hkey;  // [hcap] element offset of the node's population 0, plus 1 (0: empty)
+    int* hV;                   // [hcap] population stride (V) of the node's replica
+    long long* hsum;           // [18][hcap] fixed-point sums of the moving populations' sources
+    unsigned hcap;             // power of two, or 0 without the trilinear stencil
     int obs_every, obs_cap;
     int ntot;
 };

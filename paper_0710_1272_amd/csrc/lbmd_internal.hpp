@@ -20,6 +20,9 @@ struct MDDev {
     double eps, sigma2, rc2;          // WCA bead-bead: rc^2 = 2^(1/3) sigma^2
     double eps_w, sigma_w2, rcw2, rcw; // WCA bead-surface
     double rl2, half_skin2;           // Verlet list radius^2 (rc + skin)^2 and (skin/2)^2
+    int node_scan_all;                // 1: find the beads sharing a node by scanning every bead
+                                      // (the WCA cutoff is shorter than a node cell's diagonal
+                                      // sqrt(3), so such beads need not be list neighbours)
     double f_drive;                   // signed along x
     int rigid;                        // rigid bonds (SHAKE/RATTLE) instead of harmonic ones
     int shake_iter;
@@ -83,6 +86,7 @@ struct Context {
     int md_lanes = 0;                  // lanes per bead of the bead kernel (0: by bead count)
 
     bool use_graph = true;
+    bool deterministic = false;        // LB_CFG_DETERMINISTIC
     // instantiated graphs of 1..kGraphSteps steps, by (coupled, parity of cur, length)
     static constexpr int kGraphSteps = 16;
     hipGraphExec_t graphs[3][2][kGraphSteps + 1] = {};  // [StepMode][parity][length]
@@ -99,10 +103,13 @@ WorkLayout work_layout(int n_reps, int max_V, long long max_stage_nodes);
 
 // bead-buffer layout
 struct BeadLayout {
-    size_t r, v, u, fbar, node, bond_next, agg_at, agg_f, rep_of, diag, nlist, ncount, rref, rs, obs, total;
+    size_t r, v, u, fbar, node, bond_next, agg_at, agg_f, rep_of, diag, nlist, ncount, rref, rs, obs;
+    size_t hkey, hV, hsum, total;
+    unsigned hcap;
 };
-// obs_rows: rows of the observable record per replica (capacity + 1 header row; 0 = none)
-BeadLayout bead_layout(int ntot, int n_reps, size_t real_size, int obs_rows);
+// obs_rows: rows of the observable record per replica (capacity + 1 header row; 0 = none);
+// trilinear: room for the node table of the deterministic trilinear spread
+BeadLayout bead_layout(int ntot, int n_reps, size_t real_size, int obs_rows, bool trilinear);
 
 // kernel launchers (lb_kernels.hip / md_kernels.hip); all enqueue on `s`
 hipError_t launch_stream_collide(const Context& c, const void* src, void* dst, bool bump_step,

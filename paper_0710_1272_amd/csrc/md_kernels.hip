@@ -646,9 +646,10 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
         }
     }
     __syncthreads();
-    // Beads on one node at the start of the step are closer than sqrt(3) < rc, so they
-    // are bonded neighbours or in this list: flag whether a bead shares its node and
-    // whether a lower-index bead does (then it is not the node's leader).
+    // Flag whether a bead shares its node and whether a lower-index bead does (then it is
+    // not the node's leader).  Beads on one node lie in its unit cell, at most sqrt(3) apart:
+    // when the WCA cutoff rc covers that, they are bonded neighbours or in this list (which
+    // holds every non-bonded pair closer than rc); otherwise every bead's node is scanned.
     bool shared[BPT], before[BPT];
 #pragma unroll
     for (int k = 0; k < BPT; ++k) {
@@ -656,10 +657,11 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
         int sh = 0, bf = 0;
         if (own[k] && node[k] >= 0) {
             const bool ovf = cnt[k] > kNeighbourMax;
-            const int lim = ovf ? n : cnt[k] + 2;
+            const bool all = ovf || md.node_scan_all;
+            const int lim = all ? n : cnt[k] + 2;
             for (int q = gl; q < lim; q += G) {
                 int j;
-                if (ovf) j = q;
+                if (all) j = q;
                 else if (q < cnt[k]) j = lists[i + q * lstride];
                 else j = (q == cnt[k]) ? i - 1 : i + 1;
                 if (j < 0 || j >= n || j == i || NODE[j] != node[k]) continue;
@@ -1426,6 +1428,113 @@ __global__ __launch_bounds__(256) void k_spread_tri(const Replica* __restrict__ 
     }
 }
 
+// Deterministic form of step 3 with the trilinear stencil.  Floating-point adds depend on
+// their order, and the order of atomic adds changes from run to run; integer adds do not.
+// Each contribution -w_c (w_p / c_s^2) Fbar . c_p is rounded once to a multiple of 2^-48
+// (in FP64) and added as a 64-bit integer into a table entry of its node; a second pass adds
+// each node's exact sums to its populations (one rounding each) and empties the entry.
+constexpr double kFxScale = 281474976710656.0;  // 2^48
+constexpr double kFxLimit = 16384.0;            // larger contributions are dropped and flagged
+
+// slot of a key: the splitmix64 finaliser (Steele, Lea and Flood, OOPSLA 2014) as a hash
+__device__ __forceinline__ unsigned fx_hash(unsigned long long k, unsigned mask) {
+    k ^= k >> 30;
+    k *= 0xbf58476d1ce4e5b9ull;
+    k ^= k >> 27;
+    k *= 0x94d049bb133111ebull;
+    k ^= k >> 31;
+    return (unsigned)k & mask;
+}
+
+// Pass 1, one thread per bead: the table entry of every fluid node of the start-of-step
+// stencil (linear probing; the table holds at most 8 nodes a bead in 16 slots a bead, so a
+// free slot is always found), then 18 integer atomic adds into it.
+template <class Real>
+__global__ __launch_bounds__(64) void k_spread_tri_fx(const Replica* __restrict__ reps, BeadPtrs<Real> b,
+                                                      RunState* st) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= b.ntot) return;
+    const int NT = b.ntot;
+    const Replica& R = reps[b.rep_of[i]];
+    const double r[3] = {b.rs[i], b.rs[NT + i], b.rs[2 * NT + i]};
+    const double F[3] = {(double)b.fbar[i], (double)b.fbar[NT + i], (double)b.fbar[2 * NT + i]};
+    int lo[3][2];
+    double w1[3][2];
+    trilinear_axes(R, r, lo, w1);
+    const unsigned mask = b.hcap - 1;
+    unsigned flags = 0;
+    for (int c = 0; c < 8; ++c) {
+        const int g[3] = {lo[0][c & 1], lo[1][(c >> 1) & 1], lo[2][(c >> 2) & 1]};
+        if (is_solid(R, g[0], g[1], g[2])) continue;
+        const double w = w1[0][c & 1] * w1[1][(c >> 1) & 1] * w1[2][(c >> 2) & 1];
+        const unsigned long long key =
+            (unsigned long long)(R.pop_base + g[0] + (long long)R.nx * (g[1] + (long long)R.ny * g[2])) + 1ull;
+        unsigned h = fx_hash(key, mask);
+        bool found = false;
+        for (unsigned t = 0; t <= mask; ++t) {
+            const unsigned long long old = atomicCAS(&b.hkey[h], 0ull, key);
+            if (old == 0ull) b.hV[h] = R.V;  // this thread opened the entry
+            if (old == 0ull || old == key) {
+                found = true;
+                break;
+            }
+            h = (h + 1) & mask;
+        }
+        if (!found) {
+            flags |= LB_ERR_NONFINITE;
+            continue;
+        }
+        md_for_pops([&](auto P) {
+            constexpr int p = decltype(P)::value;
+            if constexpr (p != 0) {
+                double fc = 0.0;
+                if constexpr (cx_of(p) != 0) fc += cx_of(p) * F[0];
+                if constexpr (cy_of(p) != 0) fc += cy_of(p) * F[1];
+                if constexpr (cz_of(p) != 0) fc += cz_of(p) * F[2];
+                const double src = -3.0 * w_of<double>(p) * fc * w;
+                if (!(fabs(src) <= kFxLimit)) {
+                    flags |= LB_ERR_NONFINITE;
+                } else {
+                    const long long q = (long long)rint(src * kFxScale);
+                    (void)atomicAdd((unsigned long long*)&b.hsum[(size_t)(p - 1) * b.hcap + h], (unsigned long long)q);
+                }
+            }
+        });
+    }
+    if (flags) atomicOr(&st->err, flags);
+}
+
+// Pass 2, one thread per table slot: adds an occupied entry's sums to the post-collision
+// populations of its node (each node has one entry, so plain read-modify-writes) and empties
+// the entry for the next step.
+template <int S>
+__global__ __launch_bounds__(256) void k_spread_fx_apply(BeadPtrs<typename MDReal<S>::type> b,
+                                                         typename Codec<S>::T* __restrict__ dst, RunState* st,
+                                                         int bump_step) {
+    using C = Codec<S>;
+    using Rl = typename C::R;
+    const unsigned h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bump_step && h == 0) st->step += 1;
+    if (h >= b.hcap) return;
+    const unsigned long long key = b.hkey[h];
+    if (key == 0ull) return;
+    const long long V = b.hV[h];
+    typename C::T* __restrict__ base = dst + (long long)(key - 1ull);
+    md_for_pops([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        if constexpr (p != 0) {
+            long long* cell = &b.hsum[(size_t)(p - 1) * b.hcap + h];
+            const long long q = *cell;
+            if (q != 0) {
+                const Rl add = (Rl)((double)q * (1.0 / kFxScale));
+                base[(long long)p * V] = C::template store<p>(C::template load<p>(base[(long long)p * V]) + add);
+                *cell = 0;
+            }
+        }
+    });
+    b.hkey[h] = 0ull;
+}
+
 // ---------------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------------
@@ -1595,7 +1704,29 @@ hipError_t launch_interp_trilinear(const Context& c, const void* cur, hipStream_
                                      : launch_interp_tri_t<float>(c, cur, s);
 }
 
+template <int S>
+static hipError_t launch_spread_fx_t(const Context& c, void* dst, bool bump, hipStream_t s) {
+    using Real = typename MDReal<S>::type;
+    const BeadPtrs<Real> b = *(const BeadPtrs<Real>*)c.bead_ptrs;
+    const int grid = (c.ntot_beads + 63) / 64;
+    hipLaunchKernelGGL((k_spread_tri_fx<Real>), dim3(grid > 0 ? grid : 1), dim3(64), 0, s, c.d_reps, b, c.d_state);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_spread_fx_apply<S>), dim3((b.hcap + 255) / 256), dim3(256), 0, s, b,
+                       (typename Codec<S>::T*)dst, c.d_state, bump ? 1 : 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_spread(const Context& c, void* dst, bool bump, hipStream_t s) {
+    if (c.md.stencil == LB_STENCIL_TRILINEAR && c.deterministic) {
+        switch (c.storage) {
+            case LB_STORE_F64: return launch_spread_fx_t<LB_STORE_F64>(c, dst, bump, s);
+            case LB_STORE_F32: return launch_spread_fx_t<LB_STORE_F32>(c, dst, bump, s);
+            case LB_STORE_F16DEV: return launch_spread_fx_t<LB_STORE_F16DEV>(c, dst, bump, s);
+            case LB_STORE_BF16DEV: return launch_spread_fx_t<LB_STORE_BF16DEV>(c, dst, bump, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     if (c.md.stencil == LB_STENCIL_TRILINEAR) {
         switch (c.storage) {
             case LB_STORE_F64: return launch_spread_tri_t<LB_STORE_F64>(c, dst, bump, s);

@@ -20,7 +20,7 @@ LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_EUNSTABLE, LB_ESTATE, LB_ESIZE = 0, 
 LB_BC_PERIODIC, LB_BC_FREESLIP = 0, 1
 LB_STORE_F64, LB_STORE_F32, LB_STORE_F16DEV, LB_STORE_BF16DEV = 0, 1, 2, 3
 LB_MAX_WALLS = 2
-LB_CFG_NO_GRAPH, LB_CFG_AUTOTUNE = 1, 2
+LB_CFG_NO_GRAPH, LB_CFG_AUTOTUNE, LB_CFG_DETERMINISTIC = 1, 2, 4
 LB_MAP_AUTO, LB_MAP_FLAT, LB_MAP_ROWS, LB_MAP_SHIFTED = 0, 1, 2, 3
 LB_XCD_AUTO, LB_XCD_HARDWARE, LB_XCD_CONTIGUOUS = 0, -1, -2
 LB_BUF_POPS, LB_BUF_BEADS, LB_BUF_WORK = 0, 1, 2
@@ -35,7 +35,7 @@ LB_ERR_BEAD_IN_SOLID, LB_ERR_BEAD_OUTSIDE, LB_ERR_NONFINITE, LB_ERR_BOND_STRETCH
 LB_ERR_CONSTRAINT = 32
 LB_STENCIL_NGP, LB_STENCIL_TRILINEAR = 0, 1
 
-EXPORTED = ["lb_required_bytes", "lb_validate_config", "lb_init", "lb_step", "lb_couple", "md_step",
+EXPORTED = ["lb_required_bytes", "lb_validate_config", "lb_init", "lb_step", "lb_graph_prepare", "lb_couple", "md_step",
             "lb_moments", "lb_moments_bytes", "lb_moments_range", "lb_block_size", "lb_launch_shape", "lb_md_lanes", "lb_destroy",
             "lb_strerror", "lb_last_error_message"]
 
@@ -97,6 +97,7 @@ def lib():
         L.lb_validate_config.argtypes = [cp]
         L.lb_init.argtypes = [cp, C.POINTER(lbmd_buffers), C.c_void_p, C.POINTER(C.c_void_p)]
         L.lb_step.argtypes = [C.c_void_p, C.c_int, C.c_uint]
+        L.lb_graph_prepare.argtypes = [C.c_void_p, C.c_int, C.c_uint]
         L.lb_couple.argtypes = [C.c_void_p, C.c_uint]
         L.md_step.argtypes = [C.c_void_p]
         L.lb_moments.argtypes = [C.c_void_p, C.c_int, C.c_uint, C.c_void_p, C.c_size_t]
@@ -239,6 +240,12 @@ class Simulation:
         fluid at rest (hydro=False)."""
         flags = (LB_STEP_COUPLED if coupled else 0) if hydro else LB_STEP_NO_HYDRO
         _check(lib().lb_step(self.ctx, int(n), flags), "lb_step")
+
+    def prepare(self, n: int, coupled: bool = True, hydro: bool = True):
+        """Captures the HIP graphs that step(n, coupled, hydro) launches, for either buffer
+        parity, without running them."""
+        flags = (LB_STEP_COUPLED if coupled else 0) if hydro else LB_STEP_NO_HYDRO
+        _check(lib().lb_graph_prepare(self.ctx, int(n), flags), "lb_graph_prepare")
 
     def couple(self, direction: int):
         _check(lib().lb_couple(self.ctx, int(direction)), "lb_couple")

@@ -118,3 +118,14 @@ def test_md_lanes_validation():
     assert _cfg(big, md_lanes=4).validate() == B.LB_OK
     assert _cfg(big, md_lanes=8).validate() == B.LB_EINVAL
     assert _cfg(big, md_lanes=1).validate() == B.LB_OK
+
+
+def test_trilinear_node_table_in_bead_buffer():
+    # the deterministic trilinear spread keeps a node table of at least 16 slots a bead
+    # (8-byte key, 4-byte stride, 18 8-byte sums) in the bead buffer
+    reps = [_rep()]
+    ngp = _cfg(reps, MDParams(stencil=0), flags=B.LB_CFG_DETERMINISTIC)
+    tri = _cfg(reps, MDParams(stencil=1), flags=B.LB_CFG_DETERMINISTIC)
+    assert ngp.validate() == B.LB_OK and tri.validate() == B.LB_OK
+    extra = tri.required_bytes(B.LB_BUF_BEADS) - ngp.required_bytes(B.LB_BUF_BEADS)
+    assert extra >= 16 * 10 * (8 + 4 + 18 * 8)

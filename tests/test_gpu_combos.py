@@ -17,7 +17,7 @@ from workloads.configs import Replica
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("storage,pop_tol,pos_tol", [(WC.STORE_F64, 1e-11, 1e-10), (WC.STORE_F32, 2e-5, 2e-4)],
+@pytest.mark.parametrize("storage,pop_tol,pos_tol", [(WC.STORE_F64, 1e-11, 1e-10), (WC.STORE_F32, 1e-5, 1e-4)],
                          ids=["f64", "f32"])
 @pytest.mark.parametrize("stencil", [0, 1], ids=["ngp", "trilinear"])
 def test_rigid_chain_in_a_thermal_fluid(stencil, storage, pop_tol, pos_tol):

@@ -3,8 +3,8 @@
 
 * 128x64x64 / N=100 (FP32): 30 coupled steps in one call, every population and bead
   against the oracle (lattice shape autotuned, 4 lanes per bead).
-* 256x128x128 / N=400: 10 coupled steps, FP32 pointwise and FP16-deviation storage
-  against the oracle's velocity field.
+* 256x128x128 / N=400: 10 coupled steps, FP32 pointwise, and FP16- and BF16-deviation
+  storage against the oracle's velocity field.
 * 256 batched replicas (cubic 48..96, N in [20, 400]): 5 coupled steps of the whole
   batch; three sampled replicas (smallest, largest, one between) against the oracle, in
   FP32 and in the benchmark's FP16-deviation storage.
@@ -27,7 +27,7 @@ from workloads.configs import FREESLIP, Box, MDParams
 
 pytestmark = pytest.mark.gpu
 
-F32, F16 = WC.STORE_F32, WC.STORE_F16
+F32, F16, BF16 = WC.STORE_F32, WC.STORE_F16, WC.STORE_BF16
 
 
 def _autotune():
@@ -71,7 +71,10 @@ def _velocity_error(u_gpu, u_ora, fluid):
     return float(np.max(np.abs(u_gpu[:, fluid] - u_ora[:, fluid])) / np.max(np.abs(u_ora[:, fluid])))
 
 
-@pytest.mark.parametrize("storage", [F32, F16], ids=["f32", "f16dev"])
+# BF16 keeps 8 significant bits: one rounding of a deviation of ~w 0.03 is ~1e-3 of it, which
+# moves u by ~1e-3 of max|u| per step, so BF16 storage misses the 1e-3 bar that FP16 meets; it
+# is held to 1e-2 and its measured error is logged
+@pytest.mark.parametrize("storage", [F32, F16, BF16], ids=["f32", "f16dev", "bf16dev"])
 def test_c3_full_size_10_steps(storage):
     w = WC.c3_translocation(storage)
     rep = w.replicas[0]
@@ -99,7 +102,7 @@ def test_c3_full_size_10_steps(storage):
         _, uo = O.fields(box, ora.f)
         e = _velocity_error(ug, uo, fluid)
         log(f"  velocity error / max|u| {e:.2e}; |dr| {drift:.2e}")
-        assert e < 1e-3 and drift < 1e-3
+        assert e < (1e-3 if storage == F16 else 1e-2) and drift < 1e-3
 
 
 @pytest.mark.parametrize("storage", [F32, F16], ids=["f32", "f16dev"])

@@ -1,0 +1,128 @@
+"""GPU parity of the bead kernel for replicas of more than 512 beads (the 512^3 workload's
+bead population: an N = 800 chain and 64 crowder chains of 25 beads, Sec. III set-up), on a
+box the oracle can hold: 96^3 with two pore walls.
+
+Above 512 beads one lane owns a bead, the workgroup has up to 1024 threads, and each lane
+owns 1, 2 or 3 beads (700 and 1000 beads: one; 1600: two; 2400: three); above about 830
+beads the Verlet lists no longer fit the compute unit's LDS and live in global memory.
+Each bead count runs the interpolation and one bead step (M = 20 substeps) against the
+oracle, in FP64 and FP32, with WCA contacts active from the first substep; the 1000- and
+2400-bead replicas then run coupled steps against the oracle's populations and beads.
+"""
+from __future__ import annotations
+
+import dataclasses
+import functools
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests.common import gpu_sim, log, max_rel, min_tie_distance, oracle_sim
+from workloads import configs as WC
+from workloads import generate as G
+from workloads.configs import MDParams, Replica
+
+pytestmark = pytest.mark.gpu
+
+F64, F32 = WC.STORE_F64, WC.STORE_F32
+
+# (chain, crowders of 25): 700, 1000, 1600 and 2400 beads
+COUNTS = {700: (300, 16), 1000: (400, 24), 1600: (800, 32), 2400: (800, 64)}
+
+
+def _box():
+    return WC.pore_box(96, 96, 96, n_walls=2)
+
+
+def _beads(box, chain, crowders, seed):
+    """The chain grown from the pore mouth of wall 0 on the cis side and the crowders
+    anywhere clear of the walls, packed at an exclusion distance slightly inside the WCA
+    range (2^(1/6) 1.75 < 2^(1/6) 1.8) so that bead-bead repulsion acts at once."""
+    md_gen = dataclasses.replace(MDParams(), sigma=1.75)
+    rng = np.random.default_rng(seed)
+    out = [G.grow_chain(box, md_gen, chain, rng, start=G.pore_mouth(box))]
+    for _ in range(crowders):
+        out.append(G.grow_chain(box, md_gen, 25, rng, existing=np.concatenate(out), cis_only=False))
+    return np.concatenate(out)
+
+
+@functools.lru_cache(maxsize=None)
+def _case(n):
+    chain, crowders = COUNTS[n]
+    box = _box()
+    rep = Replica(box, [chain] + [25] * crowders, 7000 + n)
+    return rep, _beads(box, chain, crowders, 11 + n)
+
+
+@pytest.mark.parametrize("storage,tol", [(F64, 1e-11), (F32, 2e-4)], ids=["f64", "f32"])
+@pytest.mark.parametrize("n", sorted(COUNTS), ids=lambda n: f"beads{n}")
+def test_large_replica_md_step(n, storage, tol):
+    """INTERP + md_step: nodes, interpolated velocities, positions, velocities and Fbar."""
+    rep, beads = _case(n)
+    box, md = rep.box, MDParams()
+    assert len(beads) == n
+    rho, u = G.random_small_flow(box, 9, du=0.01)
+    ora = oracle_sim(rep, md, rho, u, beads=beads, step0=11)
+    u_o, node_o = O.interp(box, ora.f, ora.r)
+    F0, _ = O.conservative_forces(box, md, rep.chain_len, beads)
+    r_o, v_o = ora.r.copy(), ora.v.copy()
+    fbar_o, flags_o = O.md_substeps(box, md, rep.chain_len, r_o, v_o, u_o, 11, rep.seed)
+    from paper_0710_1272_amd import lbmd as B
+    log(f"  {n} beads ({COUNTS[n][0]} + {COUNTS[n][1]} x 25), storage {WC.STORE_NAMES[storage]}")
+    with gpu_sim([rep], md, storage, rho, u, beads=beads, step0=11) as sim:
+        assert sim.md_lanes == 1
+        sim.couple(B.LB_COUPLE_INTERP)
+        sim.md_step()
+        r_g, v_g = sim.beads()
+        u_g, fb_g, node_g = sim.coupling()
+        word, _ = sim.status()
+    scale_v = max(1.0, np.max(np.abs(v_o)))
+    log(f"    max|F0| {np.max(np.abs(F0)):.2f}; |du| {np.max(np.abs(u_g - u_o)):.2e} "
+        f"|dr| {np.max(np.abs(r_g - r_o)):.2e} |dv| {np.max(np.abs(v_g - v_o)):.2e} "
+        f"|dFbar| {np.max(np.abs(fb_g - fbar_o)):.2e}")
+    assert np.max(np.abs(F0)) > 0.5, "the configuration must have active contacts"
+    assert word == flags_o == 0
+    assert np.array_equal(node_g, node_o)
+    assert np.max(np.abs(u_g - u_o)) < tol
+    assert np.max(np.abs(r_g - r_o)) < tol
+    assert np.max(np.abs(v_g - v_o)) < tol * scale_v
+    assert np.max(np.abs(fb_g - fbar_o)) < tol * scale_v
+
+
+@pytest.mark.parametrize("n,storage,pop_tol,pos_tol",
+                         [(1000, F32, 1e-5, 1e-4), (2400, F32, 1e-5, 1e-4), (2400, F64, 1e-11, 1e-10)],
+                         ids=["beads1000-f32", "beads2400-f32", "beads2400-f64"])
+def test_large_replica_coupled_steps(n, storage, pop_tol, pos_tol):
+    """Coupled steps (graph-launched) of a replica that holds the 512^3 workload's bead
+    population: populations, positions, velocities, Fbar and nodes against the oracle, with
+    every nearest-node decision along the way far outside the GPU-oracle position drift."""
+    steps = 8
+    rep, beads = _case(n)
+    md = MDParams()
+    log(f"  {n} beads, {steps} coupled steps, storage {WC.STORE_NAMES[storage]}")
+    ora = oracle_sim(rep, md, beads=beads)
+    with gpu_sim([rep], md, storage, beads=beads) as sim:
+        worst = np.inf
+        for _ in range(steps):
+            ora.step(1)
+            sim.step(1)
+            r, _ = sim.beads()
+            drift = float(np.max(np.abs(r - ora.r)))
+            worst = min(worst, min_tie_distance(ora.r) / max(drift, 1e-15))
+        f = sim.populations()
+        r, v = sim.beads()
+        u_g, fb_g, node_g = sim.coupling()
+        tr = sim.transloc()
+        err_word, step = sim.status()
+    err = max_rel(f, ora.f, ~O.solid_mask(rep.box))
+    log(f"    populations max rel {err:.2e}; |dr| {np.max(np.abs(r - ora.r)):.2e}; "
+        f"NGP margin / drift {worst:.1e}; oracle flags {ora.flags}")
+    assert err_word == 0 and ora.flags == 0 and step == steps
+    assert worst > 10.0, "a nearest-node decision fell within 10x the GPU-oracle drift"
+    assert err < pop_tol
+    assert np.max(np.abs(r - ora.r)) < pos_tol
+    assert np.max(np.abs(v - ora.v)) < 100 * pos_tol
+    assert np.array_equal(node_g, ora.node)
+    assert np.max(np.abs(fb_g - ora.fbar)) < 100 * pos_tol
+    assert tr["n_t"] == O.transloc(rep.box, ora.r)[0]
