@@ -94,9 +94,11 @@ def test_large_replica_md_step(n, storage, tol):
                          [(1000, F32, 1e-5, 1e-4), (2400, F32, 1e-5, 1e-4), (2400, F64, 1e-11, 1e-10)],
                          ids=["beads1000-f32", "beads2400-f32", "beads2400-f64"])
 def test_large_replica_coupled_steps(n, storage, pop_tol, pos_tol):
-    """Coupled steps (graph-launched) of a replica that holds the 512^3 workload's bead
-    population: populations, positions, velocities, Fbar and nodes against the oracle, with
-    every nearest-node decision along the way far outside the GPU-oracle position drift."""
+    """Coupled steps of a replica that holds the 512^3 workload's bead population:
+    populations, positions, velocities, Fbar and nodes against the oracle.  Every nearest-node
+    decision must agree with the oracle's at every step.  With thousands of beads some bead
+    comes within a few FP32 drifts of a cell face in most runs (a near tie, logged): agreeing
+    decisions show that no such tie was decided differently, so the comparison stands."""
     steps = 8
     rep, beads = _case(n)
     md = MDParams()
@@ -104,12 +106,14 @@ def test_large_replica_coupled_steps(n, storage, pop_tol, pos_tol):
     ora = oracle_sim(rep, md, beads=beads)
     with gpu_sim([rep], md, storage, beads=beads) as sim:
         worst = np.inf
-        for _ in range(steps):
+        for k in range(steps):
             ora.step(1)
             sim.step(1)
             r, _ = sim.beads()
             drift = float(np.max(np.abs(r - ora.r)))
             worst = min(worst, min_tie_distance(ora.r) / max(drift, 1e-15))
+            # the nodes of this step (found at its start, before the bead substeps)
+            assert np.array_equal(sim.coupling()[2], ora.node), f"a nearest-node decision differs at step {k + 1}"
         f = sim.populations()
         r, v = sim.beads()
         u_g, fb_g, node_g = sim.coupling()
@@ -117,9 +121,9 @@ def test_large_replica_coupled_steps(n, storage, pop_tol, pos_tol):
         err_word, step = sim.status()
     err = max_rel(f, ora.f, ~O.solid_mask(rep.box))
     log(f"    populations max rel {err:.2e}; |dr| {np.max(np.abs(r - ora.r)):.2e}; "
-        f"NGP margin / drift {worst:.1e}; oracle flags {ora.flags}")
+        f"closest NGP decision / drift {worst:.1e}{' (near tie, decided alike)' if worst < 10 else ''}; "
+        f"oracle flags {ora.flags}")
     assert err_word == 0 and ora.flags == 0 and step == steps
-    assert worst > 10.0, "a nearest-node decision fell within 10x the GPU-oracle drift"
     assert err < pop_tol
     assert np.max(np.abs(r - ora.r)) < pos_tol
     assert np.max(np.abs(v - ora.v)) < 100 * pos_tol
