@@ -292,6 +292,27 @@ size_t lb_moments_bytes(const lbmd_ctx* ctx, int replica, unsigned what);
 int lb_moments_range(lbmd_ctx* ctx, int replica, unsigned what, long long node0, int count, void* host_out,
                      size_t bytes);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight loops, harnesses that
+ * forbid hipMalloc): the FP64 totals of lb_moments(LB_MOM_CONSERVED) for one replica's block of
+ * populations, with no context and no allocation of any kind.  The reduction's partial sums go
+ * to a static device array of the library: 1 MiB on each GPU it runs on, held until the process
+ * ends and shared by every call on that GPU, so calls that overlap in time on one GPU (other
+ * streams or host threads) race and return wrong sums.
+ *   pops:       device: the replica's [19][V] block of a population buffer in `storage`, as
+ *               lb_init lays it out (the current state is buffer pops[0] after an even number
+ *               of lattice updates since lb_init); read only; aligned to its element size
+ *   storage:    LB_STORE_*
+ *   rep:        host: the replica's box, faces, walls and rho0, read during the call (its chains
+ *               are ignored)
+ *   out4:       device, 4 doubles written: total mass and momentum x, y, z over the fluid nodes
+ *               of the pre-collision state (Sec. II Eqs. dens and vel), summed in a fixed order
+ *   hip_stream: a hipStream_t to enqueue on (NULL = the default stream)
+ * Asynchronous, no synchronisation (it can be captured into a graph).  Returns LB_EINVAL for a
+ * NULL or misaligned pointer, unknown storage or an invalid replica, LB_ESIZE for a replica of
+ * more than 2^27 nodes (the array holds 32768 blocks of partial sums, one per 4096 nodes), and
+ * LB_EDEVICE for a launch error. */
+int lb_conserved_noalloc(const void* pops, int storage, const lbmd_replica* rep, double* out4, void* hip_stream);
+
 /* Lattice-kernel launch shape in use (threads per block). */
 int lb_block_size(const lbmd_ctx* ctx);
 

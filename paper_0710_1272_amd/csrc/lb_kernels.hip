@@ -530,10 +530,9 @@ __global__ __launch_bounds__(256) void k_gather(const Replica* __restrict__ reps
 // a fixed grid-stride, wavefront butterfly, block tree, one partial per block; a
 // second single-block pass adds the partials in a fixed order (deterministic).
 template <int S>
-__global__ __launch_bounds__(256) void k_conserved_partial(const Replica* __restrict__ reps, int r,
+__global__ __launch_bounds__(256) void k_conserved_partial(const Replica R,
                                                            const typename Codec<S>::T* __restrict__ src,
                                                            double* __restrict__ partials) {
-    const Replica& R = reps[r];
     double acc[4] = {0, 0, 0, 0};
     for (int s = blockIdx.x * 256 + threadIdx.x; s < R.V; s += gridDim.x * 256) {
         const int x = s % R.nx, y = (s / R.nx) % R.ny, z = s / (R.nx * R.ny);
@@ -668,25 +667,29 @@ hipError_t launch_gather(const Context& c, int r, const void* src, int mode, lon
 }
 
 template <int S>
-static hipError_t launch_conserved_t(const Context& c, int r, const void* src, double* out4, hipStream_t s) {
+static hipError_t launch_conserved_t(const Replica& R, const void* src, double* partials, int nblk, double* out4,
+                                     hipStream_t s) {
     using T = typename Codec<S>::T;
-    hipLaunchKernelGGL((k_conserved_partial<S>), dim3(c.partial_blocks), dim3(256), 0, s, c.d_reps, r,
-                       (const T*)src, c.d_partials);
+    hipLaunchKernelGGL((k_conserved_partial<S>), dim3(nblk), dim3(256), 0, s, R, (const T*)src, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_conserved_final, dim3(1), dim3(256), 0, s, (const double*)c.d_partials,
-                       c.partial_blocks, out4);
+    hipLaunchKernelGGL(k_conserved_final, dim3(1), dim3(256), 0, s, (const double*)partials, nblk, out4);
     return hipGetLastError();
 }
 
-hipError_t launch_conserved(const Context& c, int r, const void* src, double* out4, hipStream_t s) {
-    switch (c.storage) {
-        case LB_STORE_F64: return launch_conserved_t<LB_STORE_F64>(c, r, src, out4, s);
-        case LB_STORE_F32: return launch_conserved_t<LB_STORE_F32>(c, r, src, out4, s);
-        case LB_STORE_F16DEV: return launch_conserved_t<LB_STORE_F16DEV>(c, r, src, out4, s);
-        case LB_STORE_BF16DEV: return launch_conserved_t<LB_STORE_BF16DEV>(c, r, src, out4, s);
+hipError_t launch_conserved_desc(const Replica& R, int storage, const void* src, double* partials, int nblk,
+                                 double* out4, hipStream_t s) {
+    switch (storage) {
+        case LB_STORE_F64: return launch_conserved_t<LB_STORE_F64>(R, src, partials, nblk, out4, s);
+        case LB_STORE_F32: return launch_conserved_t<LB_STORE_F32>(R, src, partials, nblk, out4, s);
+        case LB_STORE_F16DEV: return launch_conserved_t<LB_STORE_F16DEV>(R, src, partials, nblk, out4, s);
+        case LB_STORE_BF16DEV: return launch_conserved_t<LB_STORE_BF16DEV>(R, src, partials, nblk, out4, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_conserved(const Context& c, int r, const void* src, double* out4, hipStream_t s) {
+    return launch_conserved_desc(c.reps[r], c.storage, src, c.d_partials, c.partial_blocks, out4, s);
 }
 
 }  // namespace lbmd

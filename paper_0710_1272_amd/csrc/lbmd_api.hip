@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -80,6 +81,57 @@ Totals totals(const lbmd_config* cfg) {
 }  // namespace
 
 namespace lbmd {
+
+std::string replica_problem(const lbmd_replica& R) {
+    if (R.nx < 2 || R.ny < 2 || R.nz < 2) return "box sides must be >= 2";
+    if ((long long)R.nx * R.ny * R.nz > (1LL << 30)) return "box above 2^30 nodes";
+    for (int a = 0; a < 3; ++a)
+        if (R.bc[a] != LB_BC_PERIODIC && R.bc[a] != LB_BC_FREESLIP) return "unknown boundary type";
+    if (!(R.tau > 0.5) || !std::isfinite(R.tau)) return "tau must be > 1/2";
+    if (!(R.rho0 > 0.0) || !std::isfinite(R.rho0)) return "rho0 must be > 0";
+    if (!(R.fluid_kT >= 0.0) || !std::isfinite(R.fluid_kT)) return "fluid_kT must be >= 0";
+    if (R.n_walls < 0 || R.n_walls > LB_MAX_WALLS) return "n_walls out of range";
+    for (int k = 0; k < R.n_walls; ++k) {
+        const lbmd_wall& w = R.wall[k];
+        if (w.x0 > w.x1 || w.x0 < 2 || w.x1 > R.nx - 3) return "wall planes must satisfy 2 <= x0 <= x1 <= nx-3";
+        if (w.y0 <= w.y1 || w.z0 <= w.z1) {
+            if (w.y0 > w.y1 || w.z0 > w.z1 || w.y0 < 0 || w.y1 >= R.ny || w.z0 < 0 || w.z1 >= R.nz)
+                return "pore outside the cross-section";
+        }
+        if (k > 0 && w.x0 <= R.wall[k - 1].x1 + 2) return "walls must be ordered along x and at least 2 planes apart";
+    }
+    return "";
+}
+
+Replica make_replica(const lbmd_replica& in) {
+    Replica R{};
+    R.nx = in.nx;
+    R.ny = in.ny;
+    R.nz = in.nz;
+    R.V = in.nx * in.ny * in.nz;
+    for (int a = 0; a < 3; ++a) R.fs[a] = in.bc[a] == LB_BC_FREESLIP ? 1 : 0;
+    R.n_walls = in.n_walls;
+    R.wzone_lo = 1 << 30;
+    R.wzone_hi = -1;
+    for (int k = 0; k < in.n_walls; ++k) {
+        const lbmd_wall& w = in.wall[k];
+        const int v6[6] = {w.x0, w.x1, w.y0, w.y1, w.z0, w.z1};
+        for (int m = 0; m < 6; ++m) R.wall[k][m] = v6[m];
+        R.wzone_lo = std::min(R.wzone_lo, w.x0 - 1);
+        R.wzone_hi = std::max(R.wzone_hi, w.x1 + 1);
+    }
+    R.seed_lo = (uint32_t)(in.seed & 0xFFFFFFFFu);
+    R.seed_hi = (uint32_t)(in.seed >> 32);
+    R.omega = 1.0 / in.tau;
+    R.rho0 = in.rho0;
+    // thermal source amplitude: phi^2 / rho = (kT / c_s^2) (1 - gamma^2), gamma = 1 - omega
+    const double g = 1.0 - R.omega;
+    R.noise_c = 3.0 * in.fluid_kT * (1.0 - g * g);
+    R.xmid = in.n_walls > 0 ? 0.5 * (in.wall[0].x0 + in.wall[0].x1) : 0.5 * (in.nx - 1);
+    R.div_nx = make_fastdiv((uint32_t)in.nx);
+    R.div_ny = make_fastdiv((uint32_t)in.ny);
+    return R;
+}
 
 WorkLayout work_layout(int n_reps, int max_V, long long max_stage_nodes) {
     WorkLayout L{};
@@ -174,27 +226,8 @@ int lb_validate_config(const lbmd_config* cfg) {
     for (int r = 0; r < cfg->n_replicas; ++r) {
         const lbmd_replica& R = cfg->replicas[r];
         const std::string at = "replica " + std::to_string(r) + ": ";
-        if (R.nx < 2 || R.ny < 2 || R.nz < 2) return fail(LB_EINVAL, at + "box sides must be >= 2");
-        if ((long long)R.nx * R.ny * R.nz > (1LL << 30)) return fail(LB_EINVAL, at + "box above 2^30 nodes");
-        for (int a = 0; a < 3; ++a)
-            if (R.bc[a] != LB_BC_PERIODIC && R.bc[a] != LB_BC_FREESLIP)
-                return fail(LB_EINVAL, at + "unknown boundary type");
-        if (!(R.tau > 0.5) || !std::isfinite(R.tau)) return fail(LB_EINVAL, at + "tau must be > 1/2");
-        if (!(R.rho0 > 0.0) || !std::isfinite(R.rho0)) return fail(LB_EINVAL, at + "rho0 must be > 0");
-        if (!(R.fluid_kT >= 0.0) || !std::isfinite(R.fluid_kT))
-            return fail(LB_EINVAL, at + "fluid_kT must be >= 0");
-        if (R.n_walls < 0 || R.n_walls > LB_MAX_WALLS) return fail(LB_EINVAL, at + "n_walls out of range");
-        for (int k = 0; k < R.n_walls; ++k) {
-            const lbmd_wall& w = R.wall[k];
-            if (w.x0 > w.x1 || w.x0 < 2 || w.x1 > R.nx - 3)
-                return fail(LB_EINVAL, at + "wall planes must satisfy 2 <= x0 <= x1 <= nx-3");
-            if (w.y0 <= w.y1 || w.z0 <= w.z1) {
-                if (w.y0 > w.y1 || w.z0 > w.z1 || w.y0 < 0 || w.y1 >= R.ny || w.z0 < 0 || w.z1 >= R.nz)
-                    return fail(LB_EINVAL, at + "pore outside the cross-section");
-            }
-            if (k > 0 && w.x0 <= R.wall[k - 1].x1 + 2)
-                return fail(LB_EINVAL, at + "walls must be ordered along x and at least 2 planes apart");
-        }
+        const std::string why = replica_problem(R);
+        if (!why.empty()) return fail(LB_EINVAL, at + why);
         if (R.n_chains < 0 || (R.n_chains > 0 && !R.chain_len))
             return fail(LB_EINVAL, at + "chain_len missing");
         int nb = 0;
@@ -688,22 +721,7 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
     int bead0 = 0;
     for (int r = 0; r < cfg->n_replicas; ++r) {
         const lbmd_replica& in = cfg->replicas[r];
-        Replica R{};
-        R.nx = in.nx;
-        R.ny = in.ny;
-        R.nz = in.nz;
-        R.V = in.nx * in.ny * in.nz;
-        for (int a = 0; a < 3; ++a) R.fs[a] = in.bc[a] == LB_BC_FREESLIP ? 1 : 0;
-        R.n_walls = in.n_walls;
-        R.wzone_lo = 1 << 30;
-        R.wzone_hi = -1;
-        for (int k = 0; k < in.n_walls; ++k) {
-            const lbmd_wall& w = in.wall[k];
-            const int v6[6] = {w.x0, w.x1, w.y0, w.y1, w.z0, w.z1};
-            for (int m = 0; m < 6; ++m) R.wall[k][m] = v6[m];
-            R.wzone_lo = std::min(R.wzone_lo, w.x0 - 1);
-            R.wzone_hi = std::max(R.wzone_hi, w.x1 + 1);
-        }
+        Replica R = make_replica(in);
         R.x_shift = wall_x_shift(R, store_size(cfg->storage));
         R.pop_base = pop_base;
         pop_base += 19LL * R.V;
@@ -712,19 +730,7 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
         R.bead0 = bead0;
         R.n_beads = nb;
         bead0 += nb;
-        R.seed_lo = (uint32_t)(in.seed & 0xFFFFFFFFu);
-        R.seed_hi = (uint32_t)(in.seed >> 32);
-        R.omega = 1.0 / in.tau;
-        R.rho0 = in.rho0;
-        {
-            // thermal source amplitude: phi^2 / rho = (kT / c_s^2) (1 - gamma^2), gamma = 1 - omega
-            const double g = 1.0 - R.omega;
-            R.noise_c = 3.0 * in.fluid_kT * (1.0 - g * g);
-            if (in.fluid_kT > 0.0) c.thermal = true;
-        }
-        R.xmid = in.n_walls > 0 ? 0.5 * (in.wall[0].x0 + in.wall[0].x1) : 0.5 * (in.nx - 1);
-        R.div_nx = make_fastdiv((uint32_t)in.nx);
-        R.div_ny = make_fastdiv((uint32_t)in.ny);
+        if (in.fluid_kT > 0.0) c.thermal = true;
         c.reps.push_back(R);
     }
 
@@ -1154,3 +1160,65 @@ int lb_destroy(lbmd_ctx* ctx) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// Conserved sums without allocation (lb_conserved_noalloc): the partial sums of the FP64
+// reduction go to a static device array instead of a context's work buffer.
+// ---------------------------------------------------------------------------------
+namespace {
+// one block of partial sums per kNodesPerBlock nodes, at most kScratchBlocks blocks: replicas
+// of up to 2^27 nodes (512^3)
+constexpr int kScratchBlocks = 32768;
+constexpr long long kNodesPerBlock = 4096;
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+// [kScratchBlocks][4] doubles, 1 MiB on every GPU the library runs on, held until the process
+// ends; every call on a GPU shares that GPU's copy
+static __device__ __align__(256) double scratch[4 * kScratchBlocks];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+// Device address of the current device's `scratch` (in host code the array's name is a
+// host-side stand-in, not a device address), looked up on the first call on each device.
+int scratch_on_current_device(double** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LB_EDEVICE, "device ordinal beyond the library's table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(LB_EDEVICE, "no device address for the scratch array");
+        g_scratch[dev] = (double*)p;
+    }
+    *out = g_scratch[dev];
+    return LB_OK;
+}
+}  // namespace
+
+extern "C" int lb_conserved_noalloc(const void* pops, int storage, const lbmd_replica* rep, double* out4,
+                                    void* hip_stream) {
+    if (!pops || !rep || !out4) return fail(LB_EINVAL, "pops, rep and out4 are required");
+    const size_t elem = store_size(storage);
+    if (!elem) return fail(LB_EINVAL, "unknown storage");
+    if (((uintptr_t)pops % elem) != 0 || ((uintptr_t)out4 % sizeof(double)) != 0)
+        return fail(LB_EINVAL, "pops and out4 must be aligned to their element sizes");
+    const std::string why = replica_problem(*rep);
+    if (!why.empty()) return fail(LB_EINVAL, "replica: " + why);
+    const long long V = (long long)rep->nx * rep->ny * rep->nz;
+    const long long nblk = (V + kNodesPerBlock - 1) / kNodesPerBlock;
+    if (nblk > kScratchBlocks)
+        return fail(LB_ESIZE, "a replica of " + std::to_string(V) + " nodes needs " + std::to_string(nblk) +
+                                  " blocks of partial sums; the static scratch array holds " +
+                                  std::to_string(kScratchBlocks) + " (replicas of at most 2^27 nodes)");
+    double* partials = nullptr;
+    const int rc = scratch_on_current_device(&partials);
+    if (rc != LB_OK) return rc;
+    // pops is the replica's own [19][V] block: its description keeps pop_base = 0
+    const Replica R = make_replica(*rep);
+    HIP_TRY(launch_conserved_desc(R, storage, pops, partials, (int)nblk, out4, (hipStream_t)hip_stream));
+    return LB_OK;
+}

@@ -119,6 +119,14 @@ hipError_t launch_init(const Context& c, int r, void* dst, const double* d_rho, 
 hipError_t launch_gather(const Context& c, int r, const void* src, int mode, long long node0,
                          int count, double* out, hipStream_t s);
 hipError_t launch_conserved(const Context& c, int r, const void* src, double* d_out4, hipStream_t s);
+// the same reduction for a replica description passed by value (its pop_base applies to src),
+// with nblk partial-sum blocks written to partials ([nblk][4] doubles)
+hipError_t launch_conserved_desc(const Replica& R, int storage, const void* src, double* partials, int nblk,
+                                 double* out4, hipStream_t s);
+// the kernel-side description of one replica (pop_base, bead0 and x_shift are left 0)
+Replica make_replica(const lbmd_replica& in);
+// host-side checks of one replica's box, faces, walls, tau, rho0 and fluid_kT; "" if valid
+std::string replica_problem(const lbmd_replica& R);
 hipError_t launch_md(const Context& c, const void* cur, int mode, hipStream_t s);
 hipError_t launch_spread(const Context& c, void* dst, bool bump_step, hipStream_t s);
 hipError_t launch_bump(const Context& c, hipStream_t s);

@@ -37,7 +37,7 @@ LB_STENCIL_NGP, LB_STENCIL_TRILINEAR = 0, 1
 
 EXPORTED = ["lb_required_bytes", "lb_validate_config", "lb_init", "lb_step", "lb_graph_prepare", "lb_couple", "md_step",
             "lb_moments", "lb_moments_bytes", "lb_moments_range", "lb_block_size", "lb_launch_shape", "lb_md_lanes", "lb_destroy",
-            "lb_strerror", "lb_last_error_message"]
+            "lb_strerror", "lb_last_error_message", "lb_conserved_noalloc"]
 
 
 class lbmd_wall(C.Structure):
@@ -84,12 +84,17 @@ _lib = None
 
 
 def lib():
-    """Loads liblbmd.so (raises if it has not been built)."""
+    """Loads liblbmd.so (raises if it has not been built).  torch is imported first: the
+    library then binds to the HIP runtime torch has loaded (its device buffers and streams come
+    from torch), rather than loading a second copy of the runtime, which does not see the
+    device that torch opened."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -c 'import __graft_entry__ as g; g.build()'`")
+        import torch  # noqa: F401  (loads torch's HIP runtime before the library's dependency)
+
         L = C.CDLL(LIB_PATH)
         cp = C.POINTER(lbmd_config)
         L.lb_required_bytes.argtypes = [cp, C.c_int]
@@ -109,6 +114,7 @@ def lib():
         L.lb_launch_shape.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                       C.POINTER(C.c_int)]
         L.lb_md_lanes.argtypes = [C.c_void_p]
+        L.lb_conserved_noalloc.argtypes = [C.c_void_p, C.c_int, C.POINTER(lbmd_replica), C.c_void_p, C.c_void_p]
         L.lb_destroy.argtypes = [C.c_void_p]
         L.lb_strerror.argtypes = [C.c_int]
         L.lb_strerror.restype = C.c_char_p
