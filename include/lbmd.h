@@ -174,6 +174,8 @@ typedef struct lbmd_config {
                             the planes within one node of a wall share as few waves as
                             possible (the other waves skip the bounce-back tests); the same
                             as flat unless nx is a multiple of 64 and the replica has walls */
+#define LB_MAP_FLAT2 4   /* two nodes per lane, 64 apart (a wave takes 128 consecutive nodes):
+                            twice the bytes in flight per wave; blocks of 128-512 threads */
 /* xcd_order (a value C > 0 deals chunks of C consecutive tiles round-robin to the XCDs) */
 #define LB_XCD_AUTO 0        /* contiguous for one replica, hardware order for several */
 #define LB_XCD_HARDWARE (-1) /* blocks in launch order (the hardware deals them round-robin) */
@@ -198,7 +200,8 @@ typedef struct lbmd_ctx lbmd_ctx;
 size_t lb_required_bytes(const lbmd_config* cfg, int which);
 
 /* Checks a configuration on the host, without touching the device.  Rejects
- * tau <= 1/2, boxes below 2 nodes, walls or pores outside the box, walls closer
+ * tau <= 1/2, boxes below 2 nodes, boxes above 2^30 nodes or whose one population exceeds
+ * 4 GiB (FP64 storage: 2^29 nodes), walls or pores outside the box, walls closer
  * than 2 nodes to a periodic x face, M < 1, an unstable bond/substep ratio
  * (2 sqrt(k/m)/M >= 2, the kick-drift stability limit), chain lengths that do
  * not add up, and unknown storage. Returns LB_OK or LB_EINVAL. */
@@ -322,6 +325,21 @@ int lb_block_size(const lbmd_ctx* ctx);
  * 160 MB, so they are streamed past the last-level cache; 0: they stay cached between
  * steps).  Any pointer may be NULL.  Returns LB_OK or LB_EINVAL for a NULL context. */
 int lb_launch_shape(const lbmd_ctx* ctx, int* block, int* mapping, int* xcd_order, int* nt_stores);
+
+/* Measurement reference for the lattice kernel (the streaming of Eq. lbe without the collision):
+ * one launch that reads the 19 populations of every node of the current state at the lattice
+ * kernel's pull addresses (the node index minus c_p's offset, wrapped into the replica; no face
+ * or wall handling) and writes them unchanged to the node's slots in the other population
+ * buffer, with the launch shape in use (block size, XCD tile order, store policy; one node per
+ * lane).  Its duration bounds what the lattice kernel's access pattern reaches on this GPU.
+ * alternate = 0: the copy overwrites the other buffer, which the next lattice update rewrites
+ * wherever a later step reads it; the current state is unchanged.  alternate != 0: the copy
+ * becomes the current state, so that back-to-back copies alternate between the two buffers as
+ * lattice updates do (repeated copies out of one buffer find it in the last-level cache when
+ * both buffers together fit there, which lattice updates do not); the populations are then a
+ * shifted copy with no physical meaning, and the context should only be measured or destroyed
+ * afterwards.  Asynchronous. */
+int lb_pattern_copy(lbmd_ctx* ctx, int alternate);
 
 /* Lanes per bead of the bead kernel in use (1, 2, 4, 8 or 16; each bead's neighbour
  * loop is split over its lanes), 0 if no replica has beads, LB_EINVAL for a NULL

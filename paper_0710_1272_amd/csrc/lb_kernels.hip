@@ -9,6 +9,7 @@
 // non-temporal.  Per replica the populations form a [19][V] block with x fastest;
 // 16-bit storage keeps s_p (f_p - w_p rho0).  HBM traffic per fluid node is
 // 19 loads + 19 stores of the storage type, the kernel's roofline.
+#include <type_traits>
 #include <utility>
 
 #include "lbmd_internal.hpp"
@@ -52,20 +53,100 @@ __device__ __forceinline__ int replica_of_tile(const int* __restrict__ prefix, i
     return lo;
 }
 
-enum GatherKind { G_FAST = 0, G_WALL = 1, G_GENERIC = 2 };
+// Solidity of the 27 nodes (x+dx, y+dy, z+dz), dx, dy, dz in {-1, 0, 1}, as bit
+// 9(dx+1) + 3(dy+1) + (dz+1): a neighbour is solid when its x plane is a wall plane and its
+// (y, z) lies outside that wall's pore.
+__device__ __forceinline__ unsigned solid_neighbours(const Replica& R, int x, int y, int z) {
+    unsigned solid27 = 0u;
+#pragma unroll
+    for (int k = 0; k < LB_MAX_WALLS; ++k) {
+        if (k >= R.n_walls) break;
+        const int* w = R.wall[k];
+        unsigned bx = 0, by = 0, bz = 0;
+#pragma unroll
+        for (int d = -1; d <= 1; ++d) {
+            bx |= (unsigned)(x + d >= w[0] && x + d <= w[1]) << (d + 1);
+            by |= (unsigned)(y + d >= w[2] && y + d <= w[3]) << (d + 1);
+            bz |= (unsigned)(z + d >= w[4] && z + d <= w[5]) << (d + 1);
+        }
+        // pore membership of (y+dy, z+dz) for the 9 combinations, bit 3(dy+1) + (dz+1)
+        unsigned m = 0;
+        if (pore_open(w)) {
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dz = 0; dz < 3; ++dz)
+                    m |= (((by >> dy) & (bz >> dz)) & 1u) << (3 * dy + dz);
+        }
+        const unsigned closed = ~m & 0x1FFu;
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) solid27 |= (0u - ((bx >> dx) & 1u)) & (closed << (9 * dx));
+    }
+    return solid27;
+}
+
+// whether x lies within one plane of a wall (only such nodes have solid sources)
+__device__ __forceinline__ bool in_wall_zone(const Replica& R, int x) {
+    bool zone = false;
+#pragma unroll
+    for (int k = 0; k < LB_MAX_WALLS; ++k) {
+        if (k >= R.n_walls) break;
+        zone = zone || (x >= R.wall[k][0] - 1 && x <= R.wall[k][1] + 1);
+    }
+    return zone;
+}
+
+enum GatherKind { G_INTERIOR = 0, G_FAST = 1, G_WALL_PLANE = 2, G_WALL = 3, G_GENERIC = 4 };
+
+// Element `node` of a population block that starts at the wave-uniform pointer bp.  The byte
+// offset is formed in 32 bits (a replica's population block holds at most 4 GiB, which
+// lb_validate_config enforces), so the load takes the scalar-base plus 32-bit-offset form
+// and the address costs one vector instruction instead of a 64-bit multiply-add.
+template <class T>
+__device__ __forceinline__ T ld32(const T* __restrict__ bp, int node) {
+    return *(const T*)((const char*)bp + (unsigned)node * (unsigned)sizeof(T));
+}
 
 // Incoming populations of one lane of the flattened mapping (64 consecutive nodes
-// per wave, possibly spanning rows).
-//  G_GENERIC: any lane (full resolver, used by waves touching a y/z face);
-//  G_WALL:    y and z interior, lanes may neighbour a wall (solid test per source);
-//  G_FAST:    y and z interior, no wall within one node (only x faces need care).
-template <int S, int KIND>
-__device__ __forceinline__ void gather19(const Replica& R, const typename Codec<S>::T* __restrict__ src,
-                                         int idx, int x, int y, int z, typename Codec<S>::R* f) {
+// per wave, possibly spanning rows), as stored numbers (Codec::load_raw).
+//  G_GENERIC:    any lane (full resolver, used by waves touching a y/z face);
+//  G_WALL:       y and z interior, lanes may neighbour a wall and its pore (solid test per
+//                source over the 27 neighbours);
+//  G_WALL_PLANE: y and z interior, lanes may neighbour a wall but lie at least two nodes from
+//                its pore in y or z, so that a source is solid exactly when its x plane is a
+//                wall plane: only populations with c_x != 0 can bounce, on two per-lane bits;
+//  G_FAST:       y and z interior, no wall within one node (only x faces need care);
+//  G_INTERIOR:   no lane on any face or within one node of a wall (no test at all).
+// Outside G_GENERIC each population is read from its own block at a 32-bit offset; a
+// free-slip x face (the reflected population at the node itself) and a solid source (the
+// node's own population opp(p), half-way bounce-back) are loads of their own, taken only
+// by the lanes that need them.
+// RAW: f receives the stored elements themselves (decoded later by the caller), so that no
+// conversion sits between the loads of two nodes gathered one after the other.
+template <int S, int KIND, bool RAW = false>
+__device__ __forceinline__ void gather19(
+    const Replica& R, const typename Codec<S>::T* __restrict__ src, int idx, int x, int y, int z,
+    std::conditional_t<RAW, typename Codec<S>::T, typename Codec<S>::R>* f) {
     using C = Codec<S>;
+    using T = typename C::T;
+    auto cv = [](T v) {
+        if constexpr (RAW) return v;
+        else return C::load_raw(v);
+    };
     const long long V = R.V;
     const int nx = R.nx, nxy = R.nx * R.ny;
-    const typename C::T* __restrict__ base = src + R.pop_base;
+    const T* __restrict__ base = src + R.pop_base;
+    if constexpr (KIND == G_GENERIC) {
+        for_pops([&](auto P) {
+            constexpr int p = decltype(P)::value;
+            int q;
+            const int node = pull_source<p>(R, x, y, z, &q);
+            // q differs from p only by reflections or reversal, which keep the weight
+            // class, so the codec scale of p applies to slot q
+            f[p] = cv(base[(long long)q * V + node]);
+        });
+        return;
+    }
     // per-wall 3-bit masks: bit (d+1) set when x+d is a wall plane / y+d, z+d in the pore.
     // 16-bit storage (half the bytes per node, so the sweep is closer to issue-bound) folds
     // them once into the solidity of the 27 neighbours (x+dx, y+dy, z+dz), bit
@@ -75,83 +156,116 @@ __device__ __forceinline__ void gather19(const Replica& R, const typename Codec<
     unsigned mx[LB_MAX_WALLS] = {0u, 0u}, mp[LB_MAX_WALLS] = {0u, 0u};
     unsigned solid27 = 0u;
     if constexpr (KIND == G_WALL) {
+        if constexpr (kMask27) {
+            solid27 = solid_neighbours(R, x, y, z);
+        } else {
 #pragma unroll
-        for (int k = 0; k < LB_MAX_WALLS; ++k) {
-            if (k >= R.n_walls) break;
-            const int* w = R.wall[k];
-            unsigned bx = 0, by = 0, bz = 0;
+            for (int k = 0; k < LB_MAX_WALLS; ++k) {
+                if (k >= R.n_walls) break;
+                const int* w = R.wall[k];
+                unsigned bx = 0, by = 0, bz = 0;
 #pragma unroll
-            for (int d = -1; d <= 1; ++d) {
-                bx |= (unsigned)(x + d >= w[0] && x + d <= w[1]) << (d + 1);
-                by |= (unsigned)(y + d >= w[2] && y + d <= w[3]) << (d + 1);
-                bz |= (unsigned)(z + d >= w[4] && z + d <= w[5]) << (d + 1);
-            }
-            // pore membership of (y+dy, z+dz) for the 9 combinations, bit 3*(dy+1)+(dz+1)
-            unsigned m = 0;
-            if (pore_open(w)) {
+                for (int d = -1; d <= 1; ++d) {
+                    bx |= (unsigned)(x + d >= w[0] && x + d <= w[1]) << (d + 1);
+                    by |= (unsigned)(y + d >= w[2] && y + d <= w[3]) << (d + 1);
+                    bz |= (unsigned)(z + d >= w[4] && z + d <= w[5]) << (d + 1);
+                }
+                // pore membership of (y+dy, z+dz) for the 9 combinations, bit 3*(dy+1)+(dz+1)
+                unsigned m = 0;
+                if (pore_open(w)) {
 #pragma unroll
-                for (int dy = 0; dy < 3; ++dy)
+                    for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-                    for (int dz = 0; dz < 3; ++dz)
-                        m |= (((by >> dy) & (bz >> dz)) & 1u) << (3 * dy + dz);
-            }
-            if constexpr (kMask27) {
-                // a neighbour is solid when its plane is a wall plane and (y, z) is outside the pore
-                const unsigned closed = ~m & 0x1FFu;
-#pragma unroll
-                for (int dx = 0; dx < 3; ++dx) solid27 |= (0u - ((bx >> dx) & 1u)) & (closed << (9 * dx));
-            } else {
+                        for (int dz = 0; dz < 3; ++dz)
+                            m |= (((by >> dy) & (bz >> dz)) & 1u) << (3 * dy + dz);
+                }
                 mx[k] = bx;
                 mp[k] = m;
             }
         }
     }
+    // G_WALL_PLANE: whether the planes x - 1 and x + 1 are wall planes (a fluid node far from
+    // the pores is not on one itself, so its c_x = 0 sources are fluid)
+    bool solid_m = false, solid_p = false;
+    if constexpr (KIND == G_WALL_PLANE) {
+#pragma unroll
+        for (int k = 0; k < LB_MAX_WALLS; ++k) {
+            if (k >= R.n_walls) break;
+            solid_m = solid_m || (x - 1 >= R.wall[k][0] && x - 1 <= R.wall[k][1]);
+            solid_p = solid_p || (x + 1 >= R.wall[k][0] && x + 1 <= R.wall[k][1]);
+        }
+    }
+    const bool xlo = x == 0, xhi = x == nx - 1, fsx = R.fs[0] != 0;
     for_pops([&](auto P) {
         constexpr int p = decltype(P)::value;
         constexpr int cx = cx_of(p), cy = cy_of(p), cz = cz_of(p);
-        int node, q;
-        if constexpr (KIND == G_GENERIC) {
-            node = pull_source<p>(R, x, y, z, &q);
-        } else {
-            q = p;
-            node = idx - (cx + cy * nx + cz * nxy);
-            if constexpr (cx == 1) {
-                if (x == 0) {
-                    constexpr int m = mirror_of(p, 0);
-                    if (R.fs[0]) { node += 1; q = m; }
-                    else node += nx;
-                }
-            }
-            if constexpr (cx == -1) {
-                if (x == nx - 1) {
-                    constexpr int m = mirror_of(p, 0);
-                    if (R.fs[0]) { node -= 1; q = m; }
-                    else node -= nx;
-                }
-            }
-            if constexpr (KIND == G_WALL && p != 0) {
-                // source offset -c: neighbour bit 9(1 - c_x) + 3(1 - c_y) + (1 - c_z), or bit
-                // (1 - c) of each wall's masks
-                bool solid = false;
-                if constexpr (kMask27) {
-                    constexpr int bit = 9 * (1 - cx) + 3 * (1 - cy) + (1 - cz);
-                    solid = (solid27 >> bit) & 1u;
-                } else {
-#pragma unroll
-                    for (int k = 0; k < LB_MAX_WALLS; ++k) {
-                        if (k >= R.n_walls) break;
-                        bool inx = (mx[k] >> (1 - cx)) & 1u;
-                        bool inpore = (mp[k] >> (3 * (1 - cy) + (1 - cz))) & 1u;
-                        solid = solid || (inx && !inpore);
-                    }
-                }
-                if (solid) { node = idx; q = opp_of(p); }
-            }
+        int node = idx - (cx + cy * nx + cz * nxy);
+        // at an x face the source row's node x itself (free slip, fixed below) or the
+        // periodic image
+        if constexpr (KIND != G_INTERIOR && cx == 1) {
+            if (xlo) node += fsx ? 1 : nx;
         }
-        // q differs from p only by reflections or reversal, which keep the weight
-        // class, so the codec scale of p applies to slot q
-        f[p] = C::template load<p>(base[(long long)q * V + node]);
+        if constexpr (KIND != G_INTERIOR && cx == -1) {
+            if (xhi) node -= fsx ? 1 : nx;
+        }
+        f[p] = cv(ld32(base + (long long)p * V, node));
+        if constexpr (KIND == G_WALL && p != 0) {
+            // source offset -c: neighbour bit 9(1 - c_x) + 3(1 - c_y) + (1 - c_z), or bit
+            // (1 - c) of each wall's masks
+            bool solid = false;
+            if constexpr (kMask27) {
+                constexpr int bit = 9 * (1 - cx) + 3 * (1 - cy) + (1 - cz);
+                solid = (solid27 >> bit) & 1u;
+            } else {
+#pragma unroll
+                for (int k = 0; k < LB_MAX_WALLS; ++k) {
+                    if (k >= R.n_walls) break;
+                    bool inx = (mx[k] >> (1 - cx)) & 1u;
+                    bool inpore = (mp[k] >> (3 * (1 - cy) + (1 - cz))) & 1u;
+                    solid = solid || (inx && !inpore);
+                }
+            }
+            // half-way bounce-back: the node's own population opp(p) of the last collision
+            if (solid) f[p] = cv(ld32(base + (long long)opp_of(p) * V, idx));
+        }
+        if constexpr (KIND == G_WALL_PLANE && cx != 0) {
+            if (cx == 1 ? solid_m : solid_p) f[p] = cv(ld32(base + (long long)opp_of(p) * V, idx));
+        }
     });
+    if constexpr (KIND != G_INTERIOR) {
+        // a free-slip x face: the populations arriving through it are those with c_x reflected,
+        // from the node's own plane (one branch per face, taken by the lanes on it)
+        if (fsx && xlo) {
+            for_pops([&](auto P) {
+                constexpr int p = decltype(P)::value;
+                if constexpr (cx_of(p) == 1)
+                    f[p] = cv(ld32(base + (long long)mirror_of(p, 0) * V,
+                                            idx - (cy_of(p) * nx + cz_of(p) * nxy)));
+            });
+        }
+        if (fsx && xhi) {
+            for_pops([&](auto P) {
+                constexpr int p = decltype(P)::value;
+                if constexpr (cx_of(p) == -1)
+                    f[p] = cv(ld32(base + (long long)mirror_of(p, 0) * V,
+                                            idx - (cy_of(p) * nx + cz_of(p) * nxy)));
+            });
+        }
+    }
+}
+
+// Whether (y, z) lies within one node of an open pore of a wall whose zone holds x (only then
+// can a neighbour of a fluid node next to the wall lie in the pore).
+__device__ __forceinline__ bool near_pore(const Replica& R, int x, int y, int z) {
+    bool near = false;
+#pragma unroll
+    for (int k = 0; k < LB_MAX_WALLS; ++k) {
+        if (k >= R.n_walls) break;
+        const int* w = R.wall[k];
+        near = near || (pore_open(w) && x >= w[0] - 1 && x <= w[1] + 1 && y >= w[2] - 1 && y <= w[3] + 1 &&
+                        z >= w[4] - 1 && z <= w[5] + 1);
+    }
+    return near;
 }
 
 // Row-segment work units: one wave owns up to 64 consecutive x of one row (y, z) of
@@ -174,42 +288,53 @@ __device__ __forceinline__ RowUnit row_unit(const Replica& R, int unit) {
     return u;
 }
 
-// Incoming populations of one lane of a row unit.  Face handling is uniform (the
-// wave's y and z); x faces are per lane.  WALL: the segment is within one node of a
-// wall plane, so every source is tested for solidity (bounce-back); the pore test of
-// a source depends only on (y - c_y, z - c_z) and is uniform.
+// Incoming populations of one lane of a row unit.  Face handling is uniform (the wave's
+// y and z, so the source population after a y or z reflection is uniform too); x faces
+// are per lane.  WALL: the segment is within one node of a wall plane, so every source
+// is tested for solidity (bounce-back); the pore test of a source depends only on
+// (y - c_y, z - c_z) and is uniform.
 template <int S, bool WALL>
 __device__ __forceinline__ void gather_row(const Replica& R, const typename Codec<S>::T* __restrict__ src,
                                            int idx, int x, int y, int z, typename Codec<S>::R* f) {
     using C = Codec<S>;
+    using T = typename C::T;
     const long long V = R.V;
     const int nx = R.nx, ny = R.ny, nz = R.nz, nxy = R.nx * R.ny;
-    const typename C::T* __restrict__ base = src + R.pop_base;
+    const T* __restrict__ base = src + R.pop_base;
+    const bool xlo = x == 0, xhi = x == nx - 1, fsx = R.fs[0] != 0;
     for_pops([&](auto P) {
         constexpr int p = decltype(P)::value;
         constexpr int cx = cx_of(p), cy = cy_of(p), cz = cz_of(p);
         int node = idx - (cx + cy * nx + cz * nxy);
-        bool fx = false, fy = false, fz = false;
+        bool fy = false, fz = false;
         int sy = y - cy, sz = z - cz;
-        if constexpr (cx != 0) {
-            if (x == (cx > 0 ? 0 : nx - 1)) {
-                if (R.fs[0]) { node += cx; fx = true; }
-                else node += cx * nx;
-            }
-        }
         if constexpr (cy != 0) {
             if (y == (cy > 0 ? 0 : ny - 1)) {
                 if (R.fs[1]) { node += cy * nx; fy = true; sy = y; }
-                else { node += cy * nxy; sy += cy * ny; }
+                else node += cy * nxy;
             }
         }
         if constexpr (cz != 0) {
             if (z == (cz > 0 ? 0 : nz - 1)) {
                 if (R.fs[2]) { node += cz * nxy; fz = true; sz = z; }
-                else { node += cz * (long long)nxy * nz; sz += cz * nz; }
+                else node += cz * (long long)nxy * nz;
             }
         }
-        int q = mirror_combo<p>(fx, fy, fz);
+        if constexpr (cx == 1) {
+            if (xlo) node += fsx ? 1 : nx;
+        }
+        if constexpr (cx == -1) {
+            if (xhi) node -= fsx ? 1 : nx;
+        }
+        const int q = mirror_combo<p>(false, fy, fz);  // uniform over the wave
+        f[p] = C::load_raw(ld32(base + (long long)q * V, node));
+        if constexpr (cx != 0) {
+            // free slip: the population with c_x reflected as well, from that node
+            if (fsx && (cx == 1 ? xlo : xhi)) {
+                const int m = mirror_combo<p>(true, fy, fz);
+                f[p] = C::load_raw(ld32(base + (long long)m * V, node));
+            }
+        }
         if constexpr (WALL && p != 0) {
             // walls are at least two planes away from the x faces, so x - c_x is the
             // source plane of every lane that can see a wall
@@ -221,48 +346,65 @@ __device__ __forceinline__ void gather_row(const Replica& R, const typename Code
                 const bool inpore = pore_open(w) && sy >= w[2] && sy <= w[3] && sz >= w[4] && sz <= w[5];
                 solid = solid || (!inpore && x - cx >= w[0] && x - cx <= w[1]);
             }
-            if (solid) { node = idx; q = opp_of(p); }
+            // half-way bounce-back: the node's own population opp(p) of the last collision
+            if (solid) f[p] = C::load_raw(ld32(base + (long long)opp_of(p) * V, idx));
         }
-        // q differs from p only by reflections or reversal, which keep the weight
-        // class, so the codec scale of p applies to slot q
-        f[p] = C::template load<p>(base[(long long)q * V + node]);
     });
 }
 
-// BGK relaxation of one node, in place on f (full populations or deviations).
+// BGK relaxation of one node (Eq. lbe with the f_eq equation), in place on the stored numbers
+// h_p = k_p (f_p - o_p) with k_p the codec's scale and o_p = w_p rho0 for deviation storage
+// (k_p = 1, o_p = 0 for full storage); returns rho.  The opposite populations p, opp(p) are
+// taken as pairs: their sum and difference give the moments, and they share |c.u| in f_eq:
+// f_eq,p - o_p = w_p (b + rho (4.5 (c.u)^2 - 1.5 u^2) +- 3 rho c.u) with b = sum_p (f_p - o_p),
+// that is rho - rho0 for deviation storage and rho for full storage.  The relaxation
+// h*_p = (1 - omega) h_p + omega k_p (f_eq,p - o_p) keeps every scale in a constant.
 template <int S>
-__device__ __forceinline__ typename Codec<S>::R collide(typename Codec<S>::R* f,
+__device__ __forceinline__ typename Codec<S>::R collide(typename Codec<S>::R* h,
                                                         typename Codec<S>::R omega,
                                                         typename Codec<S>::R rho0) {
-    using Rl = typename Codec<S>::R;
-    Rl m0 = 0, jx = 0, jy = 0, jz = 0;
+    using C = Codec<S>;
+    using Rl = typename C::R;
+    // moments from the pair sums and differences (the o_p cancel in j: sum_p w_p c_p = 0)
+    Rl m0 = h[0] * (Rl(1) / C::template kScale<0>), jx = 0, jy = 0, jz = 0;
     for_pops([&](auto P) {
         constexpr int p = decltype(P)::value;
-        m0 += f[p];
-        if constexpr (cx_of(p) == 1) jx += f[p];
-        if constexpr (cx_of(p) == -1) jx -= f[p];
-        if constexpr (cy_of(p) == 1) jy += f[p];
-        if constexpr (cy_of(p) == -1) jy -= f[p];
-        if constexpr (cz_of(p) == 1) jz += f[p];
-        if constexpr (cz_of(p) == -1) jz -= f[p];
+        if constexpr (p % 2 == 1) {
+            constexpr Rl is = Rl(1) / C::template kScale<p>;  // opp(p) = p + 1 shares it
+            const Rl sum = h[p] + h[p + 1], dif = h[p] - h[p + 1];
+            m0 += sum * is;
+            if constexpr (cx_of(p) != 0) jx += dif * Rl(cx_of(p) * is);
+            if constexpr (cy_of(p) != 0) jy += dif * Rl(cy_of(p) * is);
+            if constexpr (cz_of(p) != 0) jz += dif * Rl(cz_of(p) * is);
+        }
     });
-    // deviation storage: m0 = rho - rho0 and f_eq - w rho0 = w (m0 + rho (...))
-    const Rl rho = Codec<S>::deviation ? rho0 + m0 : m0;
-    const Rl inv = Rl(1) / rho;
+    // deviation storage: m0 = rho - rho0; full storage: m0 = rho
+    const Rl rho = C::deviation ? rho0 + m0 : m0;
+    Rl inv;
+    if constexpr (sizeof(Rl) == 4) inv = __builtin_amdgcn_rcpf(rho);  // about 1 ulp
+    else inv = Rl(1) / rho;
     const Rl ux = jx * inv, uy = jy * inv, uz = jz * inv;
-    const Rl usq = Rl(1.5) * (ux * ux + uy * uy + uz * uz);
+    const Rl rus = rho * (Rl(1.5) * (ux * ux + uy * uy + uz * uz));
+    const Rl r3 = Rl(3) * rho, r45 = Rl(4.5) * rho;
+    const Rl om1 = Rl(1) - omega;
+    // omega k_p w_p per weight class (k_p is a power of two near 1/w_p)
+    const Rl cw0 = omega * (w_of<Rl>(0) * C::template kScale<0>);
+    const Rl cw1 = omega * (w_of<Rl>(1) * C::template kScale<1>);
+    const Rl cw7 = omega * (w_of<Rl>(7) * C::template kScale<7>);
+    h[0] = om1 * h[0] + cw0 * (m0 - rus);
     for_pops([&](auto P) {
         constexpr int p = decltype(P)::value;
-        constexpr Rl w = w_of<Rl>(p);
-        Rl cu = 0;
-        if constexpr (cx_of(p) != 0) cu += Rl(cx_of(p)) * ux;
-        if constexpr (cy_of(p) != 0) cu += Rl(cy_of(p)) * uy;
-        if constexpr (cz_of(p) != 0) cu += Rl(cz_of(p)) * uz;
-        const Rl poly = Rl(3) * cu + Rl(4.5) * cu * cu - usq;
-        Rl feq;
-        if constexpr (Codec<S>::deviation) feq = w * (m0 + rho * poly);
-        else feq = w * rho * (Rl(1) + poly);
-        f[p] = f[p] + omega * (feq - f[p]);
+        if constexpr (p % 2 == 1) {
+            Rl cu = 0;
+            if constexpr (cx_of(p) != 0) cu += Rl(cx_of(p)) * ux;
+            if constexpr (cy_of(p) != 0) cu += Rl(cy_of(p)) * uy;
+            if constexpr (cz_of(p) != 0) cu += Rl(cz_of(p)) * uz;
+            const Rl e = m0 + ((r45 * cu) * cu - rus);  // b + rho (4.5 cu^2 - 1.5 u^2)
+            const Rl t = r3 * cu;
+            const Rl cw = p <= 6 ? cw1 : cw7;
+            h[p] = om1 * h[p] + cw * (e + t);
+            h[p + 1] = om1 * h[p + 1] + cw * (e - t);
+        }
     });
     return rho;
 }
@@ -273,8 +415,9 @@ __device__ __forceinline__ typename Codec<S>::R collide(typename Codec<S>::R* f,
 // counters (node, step, j, 2)), Pi x = x - w (sum x + 3 c . sum c x) (no density or
 // momentum in the noise), phi^2 = (kT / c_s^2) (1 - gamma^2) rho.  Its covariance
 // mu rho (1 - gamma^2) Pi W is what keeps the equilibrium fluctuations mu rho w_p of the
-// populations through a BGK collision with rate omega = 1 - gamma.
-template <class Rl>
+// populations through a BGK collision with rate omega = 1 - gamma.  f holds the codec's stored
+// numbers, so the source of population p is added times its scale k_p.
+template <class C, class Rl>
 __device__ __forceinline__ void add_thermal(Rl* f, uint32_t node, uint32_t step, uint32_t k0, uint32_t k1,
                                             Rl phi) {
     Rl s0 = 0, sx = 0, sy = 0, sz = 0;
@@ -295,7 +438,7 @@ __device__ __forceinline__ void add_thermal(Rl* f, uint32_t node, uint32_t step,
         if constexpr (cx_of(p) != 0) sx += Rl(cx_of(p)) * eta;
         if constexpr (cy_of(p) != 0) sy += Rl(cy_of(p)) * eta;
         if constexpr (cz_of(p) != 0) sz += Rl(cz_of(p)) * eta;
-        f[p] += phi * eta;
+        f[p] += (phi * C::template kScale<p>) * eta;
     });
     for_pops([&](auto P) {
         constexpr int p = decltype(P)::value;
@@ -303,16 +446,46 @@ __device__ __forceinline__ void add_thermal(Rl* f, uint32_t node, uint32_t step,
         if constexpr (cx_of(p) != 0) m += Rl(3 * cx_of(p)) * sx;
         if constexpr (cy_of(p) != 0) m += Rl(3 * cy_of(p)) * sy;
         if constexpr (cz_of(p) != 0) m += Rl(3 * cz_of(p)) * sz;
-        f[p] -= phi * w_of<Rl>(p) * m;
+        f[p] -= phi * (w_of<Rl>(p) * C::template kScale<p>) * m;
     });
 }
 
-// Thread-to-node mappings of the lattice kernel.  MAP_SHIFTED is MAP_FLAT with every
-// x-row rotated by the replica's x_shift, chosen on the host so that the planes within one
-// node of a wall fall into as few 64-lane waves as possible: the other waves of a row then
-// take the interior gather (used when nx is a multiple of 64, so that waves are row
-// segments).
-enum LatticeMapping { MAP_FLAT = 0, MAP_ROWS = 1, MAP_SHIFTED = 2 };
+// Thread-to-node mappings of the lattice kernel.  MAP_SHIFTED is MAP_FLAT with every x-row
+// rotated by the replica's x_shift, chosen on the host so that the planes within one node of a
+// wall fall into as few 64-lane waves as possible: the other waves of a row then take the
+// gather without solid tests (used when nx is a multiple of 64, so that waves are row segments).
+// MAP_FLAT2: two nodes per lane, 64 apart (k_stream_collide_2n).
+enum LatticeMapping { MAP_FLAT = 0, MAP_ROWS = 1, MAP_SHIFTED = 2, MAP_FLAT2 = 3 };
+
+// Collision of one fluid node (Eq. lbe), the density check, and the thermal source F_p.
+template <int S, bool TH>
+__device__ __forceinline__ void relax_node(const Replica& R, typename Codec<S>::R* f, int idx,
+                                           RunState* __restrict__ st) {
+    using Rl = typename Codec<S>::R;
+    const Rl rho = collide<S>(f, (Rl)R.omega, (Rl)R.rho0);
+    if (!(rho > Rl(0)) || !(rho < Rl(1e30))) atomicOr(&st->err, LB_ERR_DENSITY);
+    if constexpr (TH) {
+        // the step counter does not move during a sweep with a thermal source
+        const Rl phi = sqrt(fmax((Rl)R.noise_c * rho, Rl(0)));
+        add_thermal<Codec<S>, Rl>(f, (uint32_t)idx, (uint32_t)st->step, R.seed_lo, R.seed_hi, phi);
+    }
+}
+
+// The slots of a solid node: never read (a fluid node bounces back off its own slots, and the
+// read-outs report zero there), but written with every sweep, the rest value w_p rho0 that
+// lb_init leaves there, so that a store instruction of a wave covers whole cache lines.  A
+// wave whose lanes skip their stores leaves partly written lines, which HBM completes with a
+// read-modify-write: in 48-96 node rows, each crossing a wall, that cost the 16-bit sweep 40 %.
+template <int S>
+__device__ __forceinline__ void rest_slots(const Replica& R, typename Codec<S>::R* f) {
+    using C = Codec<S>;
+    using Rl = typename C::R;
+    for_pops([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        if constexpr (C::deviation) f[p] = Rl(0);
+        else f[p] = w_of<Rl>(p) * (Rl)R.rho0;
+    });
+}
 
 template <int S, int BLOCK, bool NT, bool TH>
 __global__ __launch_bounds__(BLOCK) void k_stream_collide(const Replica* __restrict__ reps,
@@ -330,6 +503,7 @@ __global__ __launch_bounds__(BLOCK) void k_stream_collide(const Replica* __restr
     const Replica& R = reps[r];
     Rl f[Q];
     int idx;
+    bool solid = false;
     if (mapping == MAP_ROWS) {
         // one wave per row segment: y, z and the face decisions are wave-uniform
         constexpr int W = BLOCK / 64;
@@ -339,7 +513,7 @@ __global__ __launch_bounds__(BLOCK) void k_stream_collide(const Replica* __restr
         const int x = U.x0 + (threadIdx.x & 63);
         const int y = U.y, z = U.z;
         if (x >= R.nx) return;
-        if (is_solid(R, x, y, z)) return;  // solid nodes are never read
+        solid = is_solid(R, x, y, z);
         idx = x + R.nx * (y + R.ny * z);
         bool zone = false;
 #pragma unroll
@@ -347,13 +521,16 @@ __global__ __launch_bounds__(BLOCK) void k_stream_collide(const Replica* __restr
             if (k >= R.n_walls) break;
             zone = zone || (U.x0 <= R.wall[k][1] + 1 && U.x0 + 63 >= R.wall[k][0] - 1);
         }
-        if (zone) gather_row<S, true>(R, src, idx, x, y, z, f);
-        else gather_row<S, false>(R, src, idx, x, y, z, f);
+        if (!solid) {
+            if (zone) gather_row<S, true>(R, src, idx, x, y, z, f);
+            else gather_row<S, false>(R, src, idx, x, y, z, f);
+        }
     } else {
         // 64 consecutive nodes per wave; waves that touch a y/z face take the general
         // resolver, waves next to a wall the solid-testing one
         const int n = (tile - prefix[r]) * BLOCK + threadIdx.x;
-        bool active = n < R.V;
+        const bool inside = n < R.V;
+        bool active = inside;
         const uint32_t t = fdiv((uint32_t)n, R.div_nx);
         int x = n - (int)t * R.nx;
         if (mapping == MAP_SHIFTED) {
@@ -364,33 +541,35 @@ __global__ __launch_bounds__(BLOCK) void k_stream_collide(const Replica* __restr
         const uint32_t zz = fdiv(t, R.div_ny);
         const int y = (int)t - (int)zz * R.ny;
         const int z = (int)zz;
-        bool face = false, zone = false;
+        bool face = false, zone = false, xface = false, pore = false;
         if (active) {
             if (is_solid(R, x, y, z)) active = false;
             face = y == 0 || y == R.ny - 1 || z == 0 || z == R.nz - 1;
-#pragma unroll
-            for (int k = 0; k < LB_MAX_WALLS; ++k) {
-                if (k >= R.n_walls) break;
-                zone = zone || (x >= R.wall[k][0] - 1 && x <= R.wall[k][1] + 1);
-            }
+            zone = in_wall_zone(R, x);
+            xface = x == 0 || x == R.nx - 1;
+            pore = near_pore(R, x, y, z);
         }
         face = face && active;
         zone = zone && active;
+        xface = xface && active;
+        pore = pore && active;
         const bool any_face = __ballot(face) != 0;
         const bool any_zone = __ballot(zone) != 0;
-        if (!active) return;
-        if (any_face) gather19<S, G_GENERIC>(R, src, idx, x, y, z, f);
-        else if (any_zone) gather19<S, G_WALL>(R, src, idx, x, y, z, f);
-        else gather19<S, G_FAST>(R, src, idx, x, y, z, f);
+        const bool any_xface = __ballot(xface) != 0;
+        const bool any_pore = __ballot(pore) != 0;
+        if (!inside) return;
+        solid = !active;
+        if (active) {
+            if (any_face) gather19<S, G_GENERIC>(R, src, idx, x, y, z, f);
+            else if (any_pore) gather19<S, G_WALL>(R, src, idx, x, y, z, f);
+            else if (any_zone) gather19<S, G_WALL_PLANE>(R, src, idx, x, y, z, f);
+            else if (any_xface) gather19<S, G_FAST>(R, src, idx, x, y, z, f);
+            else gather19<S, G_INTERIOR>(R, src, idx, x, y, z, f);
+        }
     }
 
-    const Rl rho = collide<S>(f, (Rl)R.omega, (Rl)R.rho0);
-    if (!(rho > Rl(0)) || !(rho < Rl(1e30))) atomicOr(&st->err, LB_ERR_DENSITY);
-    if constexpr (TH) {
-        // the step counter does not move during a sweep with a thermal source
-        const Rl phi = sqrt(fmax((Rl)R.noise_c * rho, Rl(0)));
-        add_thermal<Rl>(f, (uint32_t)idx, (uint32_t)st->step, R.seed_lo, R.seed_hi, phi);
-    }
+    if (solid) rest_slots<S>(R, f);
+    else relax_node<S, TH>(R, f, idx, st);
 
     typename C::T* __restrict__ out = dst + R.pop_base + idx;
     const long long V = R.V;
@@ -399,14 +578,139 @@ __global__ __launch_bounds__(BLOCK) void k_stream_collide(const Replica* __restr
     if constexpr (NT) {
         for_pops([&](auto P) {
             constexpr int p = decltype(P)::value;
-            __builtin_nontemporal_store(C::template store<p>(f[p]), out + (long long)p * V);
+            __builtin_nontemporal_store(C::store_raw(f[p]), out + (long long)p * V);
         });
     } else {
         for_pops([&](auto P) {
             constexpr int p = decltype(P)::value;
-            out[(long long)p * V] = C::template store<p>(f[p]);
+            out[(long long)p * V] = C::store_raw(f[p]);
         });
     }
+}
+
+template <int S, int KIND, class E>
+__device__ __forceinline__ void gather_two(const Replica& R, const typename Codec<S>::T* __restrict__ src,
+                                           const int* n, const int* x, const int* y, const int* z, E* f0,
+                                           E* f1) {
+    constexpr bool raw = !std::is_same_v<E, typename Codec<S>::R>;
+    gather19<S, KIND, raw>(R, src, n[0], x[0], y[0], z[0], f0);
+    gather19<S, KIND, raw>(R, src, n[1], x[1], y[1], z[1], f1);
+}
+
+// One LB step for two nodes per lane, 64 apart: a wave takes 128 consecutive nodes of a
+// replica and every load still covers 64 consecutive elements.  Both nodes' 19 loads are
+// issued before the first collision, so a wave keeps twice the bytes in flight while it
+// computes (16-bit storage moves only 128 bytes per load).  Both gathers run for every lane:
+// a solid node, or a lane past the end of the replica (which takes the last node), reads
+// nodes of the box and its results are dropped; solid nodes store their rest slots.
+template <int S, int BLOCK, bool NT, bool TH>
+__global__ __launch_bounds__(BLOCK) void k_stream_collide_2n(const Replica* __restrict__ reps,
+                                                             const int* __restrict__ prefix, int n_reps,
+                                                             const typename Codec<S>::T* __restrict__ src,
+                                                             typename Codec<S>::T* __restrict__ dst,
+                                                             RunState* __restrict__ st, int bump_step,
+                                                             int xcd_chunk) {
+    using C = Codec<S>;
+    using Rl = typename C::R;
+    if (bump_step && blockIdx.x == 0 && threadIdx.x == 0) st->step += 1;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, xcd_chunk);
+    const int r = replica_of_tile(prefix, n_reps, tile);
+    const Replica& R = reps[r];
+    const int first = (tile - prefix[r]) * (2 * BLOCK) + (threadIdx.x >> 6) * 128 + (threadIdx.x & 63);
+    int n[2], x[2], y[2], z[2];
+    bool act[2], in[2];
+    bool face = false, zone = false, xface = false, pore = false;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        int m = first + 64 * k;
+        in[k] = m < R.V;
+        act[k] = in[k];
+        if (!in[k]) m = R.V - 1;
+        const uint32_t t = fdiv((uint32_t)m, R.div_nx);
+        x[k] = m - (int)t * R.nx;
+        const uint32_t zz = fdiv(t, R.div_ny);
+        y[k] = (int)t - (int)zz * R.ny;
+        z[k] = (int)zz;
+        n[k] = m;
+        // the gather kind covers every node the lane reads around, solid or not
+        face = face || y[k] == 0 || y[k] == R.ny - 1 || z[k] == 0 || z[k] == R.nz - 1;
+        zone = zone || in_wall_zone(R, x[k]);
+        xface = xface || x[k] == 0 || x[k] == R.nx - 1;
+        pore = pore || near_pore(R, x[k], y[k], z[k]);
+        act[k] = act[k] && !is_solid(R, x[k], y[k], z[k]);
+    }
+    const bool any_face = __ballot(face) != 0;
+    const bool any_zone = __ballot(zone) != 0;
+    const bool any_xface = __ballot(xface) != 0;
+    const bool any_pore = __ballot(pore) != 0;
+    if (!in[0]) return;  // then the second node is outside too
+    // 16-bit elements are gathered as stored and decoded after both nodes' loads are issued
+    using E = std::conditional_t<C::deviation, typename C::T, Rl>;
+    E g0[Q], g1[Q];
+    if (any_face) gather_two<S, G_GENERIC>(R, src, n, x, y, z, g0, g1);
+    else if (any_pore) gather_two<S, G_WALL>(R, src, n, x, y, z, g0, g1);
+    else if (any_zone) gather_two<S, G_WALL_PLANE>(R, src, n, x, y, z, g0, g1);
+    else if (any_xface) gather_two<S, G_FAST>(R, src, n, x, y, z, g0, g1);
+    else gather_two<S, G_INTERIOR>(R, src, n, x, y, z, g0, g1);
+    Rl f0[Q], f1[Q];
+    for_pops([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        if constexpr (C::deviation) {
+            f0[p] = C::load_raw(g0[p]);
+            f1[p] = C::load_raw(g1[p]);
+        } else {
+            f0[p] = g0[p];
+            f1[p] = g1[p];
+        }
+    });
+
+    const long long V = R.V;
+    typename C::T* __restrict__ out = dst + R.pop_base;
+    auto finish = [&](Rl* f, int idx, bool fluid) {
+        if (fluid) relax_node<S, TH>(R, f, idx, st);
+        else rest_slots<S>(R, f);
+        for_pops([&](auto P) {
+            constexpr int p = decltype(P)::value;
+            if constexpr (NT) __builtin_nontemporal_store(C::store_raw(f[p]), out + (long long)p * V + idx);
+            else out[(long long)p * V + idx] = C::store_raw(f[p]);
+        });
+    };
+    finish(f0, n[0], act[0]);
+    if (in[1]) finish(f1, n[1], act[1]);
+}
+
+// Same-pattern reference of the lattice kernel: every population of every node read at the
+// kernel's pull address (the node index minus c_p's offset, wrapped into the replica; no faces,
+// no solids, no arithmetic) and written unchanged to the node's own slot of the other buffer,
+// in the kernel's tile order and store policy, one node per lane.  Its bandwidth bounds what
+// the sweep's access pattern can reach.
+template <int S, int BLOCK, bool NT>
+__global__ __launch_bounds__(BLOCK) void k_pattern(const Replica* __restrict__ reps, const int* __restrict__ prefix,
+                                                   int n_reps, const typename Codec<S>::T* __restrict__ src,
+                                                   typename Codec<S>::T* __restrict__ dst, int xcd_chunk) {
+    using T = typename Codec<S>::T;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, xcd_chunk);
+    const int r = replica_of_tile(prefix, n_reps, tile);
+    const Replica& R = reps[r];
+    const long long V = R.V;
+    const long long n = (long long)(tile - prefix[r]) * BLOCK + threadIdx.x;
+    if (n >= V) return;
+    const T* __restrict__ base = src + R.pop_base;
+    T* __restrict__ out = dst + R.pop_base;
+    const long long nx = R.nx, nxy = (long long)R.nx * R.ny;
+    T v[Q];
+    for_pops([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        long long s = n - (cx_of(p) + cy_of(p) * nx + cz_of(p) * nxy);
+        if (s < 0) s += V;
+        else if (s >= V) s -= V;
+        v[p] = base[(long long)p * V + s];
+    });
+    for_pops([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        if constexpr (NT) __builtin_nontemporal_store(v[p], out + (long long)p * V + n);
+        else out[(long long)p * V + n] = v[p];
+    });
 }
 
 // ---------------------------------------------------------------------------------
@@ -448,21 +752,22 @@ __global__ __launch_bounds__(256) void k_init(const Replica* __restrict__ reps, 
     const int sx = s % R.nx, sy = (s / R.nx) % R.ny, sz = s / (R.nx * R.ny);
     const bool solid = is_solid(R, sx, sy, sz);
     typename C::T* out = dst + R.pop_base + s;
+    // the wanted pre-collision population p at node x
+    auto wanted = [&](int p, int x) -> double {
+        if (pops_in) return pops_in[(long long)p * V + x];
+        const double rho = rho_in ? rho_in[x] : R.rho0;
+        double feq[Q];
+        if (u_in) feq19(rho, u_in[x], u_in[V + x], u_in[2 * V + x], feq);
+        else feq19(rho, 0.0, 0.0, 0.0, feq);
+        return pick19(feq, p);
+    };
     for_pops([&](auto P) {
         constexpr int q = decltype(P)::value;
         double val = w_of<double>(q) * R.rho0;
+        int p;
         if (!solid) {
-            int p;
             const int x = push_target<q>(R, sx, sy, sz, &p);
-            if (pops_in) {
-                val = pops_in[(long long)p * V + x];
-            } else {
-                const double rho = rho_in ? rho_in[x] : R.rho0;
-                double feq[Q];
-                if (u_in) feq19(rho, u_in[x], u_in[V + x], u_in[2 * V + x], feq);
-                else feq19(rho, 0.0, 0.0, 0.0, feq);
-                val = pick19(feq, p);
-            }
+            val = wanted(p, x);
         }
         if constexpr (C::deviation) val -= w_of<double>(q) * R.rho0;
         out[(long long)q * V] = C::template store<q>((typename C::R)val);
@@ -585,10 +890,60 @@ __global__ __launch_bounds__(256) void k_conserved_final(const double* __restric
 template <int S, int BLOCK, bool NT, bool TH>
 static hipError_t launch_sc_n(const Context& c, const void* src, void* dst, bool bump, hipStream_t s) {
     using T = typename Codec<S>::T;
+    if (c.lat.mapping == MAP_FLAT2) {
+        if constexpr (BLOCK >= 128 && BLOCK <= 512) {
+            hipLaunchKernelGGL((k_stream_collide_2n<S, BLOCK, NT, TH>), dim3(c.lat.total_tiles), dim3(BLOCK), 0, s,
+                               c.d_reps, c.lat.d_prefix, (int)c.reps.size(), (const T*)src, (T*)dst, c.d_state,
+                               bump ? 1 : 0, c.lat_chunk);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;  // two nodes per lane: blocks of 128 to 512 threads
+        }
+    }
     hipLaunchKernelGGL((k_stream_collide<S, BLOCK, NT, TH>), dim3(c.lat.total_tiles), dim3(BLOCK), 0, s,
                        c.d_reps, c.lat.d_prefix, (int)c.reps.size(), (const T*)src, (T*)dst, c.d_state,
                        bump ? 1 : 0, c.lat_chunk, c.lat.mapping);
     return hipGetLastError();
+}
+
+template <int S, int BLOCK, bool NT>
+static hipError_t launch_pattern_n(const Context& c, const void* src, void* dst, hipStream_t s) {
+    using T = typename Codec<S>::T;
+    // the flat tile table of this block size (the rows mapping has other tiles)
+    const LatticeLaunch* L = nullptr;
+    for (const auto& l : c.lat_all)
+        if (l.block == BLOCK && l.mapping == MAP_FLAT) L = &l;
+    if (!L) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_pattern<S, BLOCK, NT>), dim3(L->total_tiles), dim3(BLOCK), 0, s, c.d_reps, L->d_prefix,
+                       (int)c.reps.size(), (const T*)src, (T*)dst, c.lat_chunk);
+    return hipGetLastError();
+}
+
+template <int S, int BLOCK>
+static hipError_t launch_pattern_t(const Context& c, const void* src, void* dst, hipStream_t s) {
+    return c.lat_nt ? launch_pattern_n<S, BLOCK, true>(c, src, dst, s) : launch_pattern_n<S, BLOCK, false>(c, src, dst, s);
+}
+
+template <int S>
+static hipError_t launch_pattern_s(const Context& c, const void* src, void* dst, hipStream_t s) {
+    switch (c.lat.block) {
+        case 64: return launch_pattern_t<S, 64>(c, src, dst, s);
+        case 128: return launch_pattern_t<S, 128>(c, src, dst, s);
+        case 256: return launch_pattern_t<S, 256>(c, src, dst, s);
+        case 512: return launch_pattern_t<S, 512>(c, src, dst, s);
+        case 1024: return launch_pattern_t<S, 1024>(c, src, dst, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pattern(const Context& c, const void* src, void* dst, hipStream_t s) {
+    switch (c.storage) {
+        case LB_STORE_F64: return launch_pattern_s<LB_STORE_F64>(c, src, dst, s);
+        case LB_STORE_F32: return launch_pattern_s<LB_STORE_F32>(c, src, dst, s);
+        case LB_STORE_F16DEV: return launch_pattern_s<LB_STORE_F16DEV>(c, src, dst, s);
+        case LB_STORE_BF16DEV: return launch_pattern_s<LB_STORE_BF16DEV>(c, src, dst, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <int S, int BLOCK>

@@ -147,9 +147,9 @@ WorkLayout work_layout(int n_reps, int max_V, long long max_stage_nodes) {
     L.stage_doubles = (size_t)(19 * stage_nodes);
     L.stage = off;
     off += align256(sizeof(double) * L.stage_doubles);
-    L.n_prefix_tables = 2 * kNumBlockSizes;
+    L.n_prefix_tables = 3 * kNumBlockSizes;
     L.prefix = off;
-    off += align256(sizeof(int) * (size_t)(n_reps + 1) * kNumBlockSizes * 2);
+    off += align256(sizeof(int) * (size_t)(n_reps + 1) * kNumBlockSizes * 3);
     L.total = off;
     return L;
 }
@@ -181,7 +181,7 @@ BeadLayout bead_layout(int ntot, int n_reps, size_t rs, int obs_rows, bool trili
         while (L.hcap < 16 * N) L.hcap <<= 1;
     }
     L.hkey = off;     off += align256((size_t)L.hcap * sizeof(unsigned long long));
-    L.hV = off;       off += align256((size_t)L.hcap * sizeof(int));
+    L.hrep = off;     off += align256((size_t)L.hcap * sizeof(int));
     L.hsum = off;     off += align256((size_t)18 * L.hcap * sizeof(long long));
     L.total = off;
     return L;
@@ -219,8 +219,10 @@ int lb_validate_config(const lbmd_config* cfg) {
         for (int b : kBlockSizes) ok = ok || b == cfg->block_size;
         if (!ok) return fail(LB_EINVAL, "block_size must be 0, 64, 128, 256, 512 or 1024");
     }
-    if (cfg->lattice_mapping < LB_MAP_AUTO || cfg->lattice_mapping > LB_MAP_SHIFTED)
+    if (cfg->lattice_mapping < LB_MAP_AUTO || cfg->lattice_mapping > LB_MAP_FLAT2)
         return fail(LB_EINVAL, "unknown lattice_mapping");
+    if (cfg->lattice_mapping == LB_MAP_FLAT2 && (cfg->block_size == 64 || cfg->block_size == 1024))
+        return fail(LB_EINVAL, "LB_MAP_FLAT2 runs blocks of 128, 256 or 512 threads");
     if (cfg->xcd_order < LB_XCD_CONTIGUOUS) return fail(LB_EINVAL, "unknown xcd_order");
     int total_beads = 0, max_beads = 0;
     for (int r = 0; r < cfg->n_replicas; ++r) {
@@ -228,6 +230,9 @@ int lb_validate_config(const lbmd_config* cfg) {
         const std::string at = "replica " + std::to_string(r) + ": ";
         const std::string why = replica_problem(R);
         if (!why.empty()) return fail(LB_EINVAL, at + why);
+        // the lattice kernel addresses one population of a replica with 32-bit byte offsets
+        if ((long long)R.nx * R.ny * R.nz * (long long)store_size(cfg->storage) > (1LL << 32))
+            return fail(LB_EINVAL, at + "one population of the box exceeds 4 GiB (FP64 storage: at most 2^29 nodes)");
         if (R.n_chains < 0 || (R.n_chains > 0 && !R.chain_len))
             return fail(LB_EINVAL, at + "chain_len missing");
         int nb = 0;
@@ -360,7 +365,7 @@ int setup_beads(Context& c, const lbmd_config* cfg) {
     p->rs = (double*)(base + L.rs);
     p->obs = (double*)(base + L.obs);
     p->hkey = (unsigned long long*)(base + L.hkey);
-    p->hV = (int*)(base + L.hV);
+    p->hrep = (int*)(base + L.hrep);
     p->hsum = (long long*)(base + L.hsum);
     p->hcap = L.hcap;
     p->obs_every = c.obs_every;
@@ -474,7 +479,7 @@ int autotune(Context& c) {
     int best_block = c.lat.block, best_chunk = c.lat_chunk, best_map = c.lat.mapping;
     bool shifted = false;
     for (const Replica& R : c.reps) shifted = shifted || R.x_shift != 0;
-    for (int map : {0, 1, 2})
+    for (int map : {0, 1, 2, 3})
     for (int b : {128, 256, 512}) {
         if (map == 2 && !shifted) continue;  // the same launches as the flat mapping
         for (int chunk : {-1, 0, 16, 64}) {
@@ -818,7 +823,7 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
 
     // tile prefix tables for every lattice block size and both thread mappings
     int* prefix_base = (int*)(wb + W.prefix);
-    for (int mi = 0; mi < 2; ++mi) {
+    for (int mi = 0; mi < 3; ++mi) {
         for (int bi = 0; bi < kNumBlockSizes; ++bi) {
             const int b = kBlockSizes[bi];
             std::vector<int> pre(c.reps.size() + 1, 0);
@@ -827,16 +832,19 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
                 long long tiles;
                 if (mi == 0) {
                     tiles = (R.V + b - 1) / b;
-                } else {
+                } else if (mi == 1) {
                     // one wave per row segment of at most 64 nodes
                     const long long units = (long long)R.ny * R.nz * ((R.nx + 63) / 64);
                     tiles = (units + b / 64 - 1) / (b / 64);
+                } else {
+                    // two nodes per lane
+                    tiles = (R.V + 2 * b - 1) / (2 * b);
                 }
                 pre[r + 1] = pre[r] + (int)tiles;
             }
             LatticeLaunch L;
             L.block = b;
-            L.mapping = mi;
+            L.mapping = mi == 2 ? 3 : mi;
             L.total_tiles = pre.back();
             L.d_prefix = prefix_base + (mi * kNumBlockSizes + bi) * (int)(c.reps.size() + 1);
             if ((rc = check(hipMemcpy(L.d_prefix, pre.data(), sizeof(int) * pre.size(), hipMemcpyHostToDevice),
@@ -856,7 +864,10 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
     for (const Replica& R : c.reps) rows_fit = rows_fit && (R.nx % 64 == 0);
     // measured: row segments win only marginally (FP32, one box), so flat is the default
     (void)rows_fit;
-    c.lat.mapping = cfg->lattice_mapping == LB_MAP_ROWS ? 1 : cfg->lattice_mapping == LB_MAP_SHIFTED ? 2 : 0;
+    c.lat.mapping = cfg->lattice_mapping == LB_MAP_ROWS      ? 1
+                    : cfg->lattice_mapping == LB_MAP_SHIFTED ? 2
+                    : cfg->lattice_mapping == LB_MAP_FLAT2   ? 3
+                                                             : 0;
     if (cfg->xcd_order == LB_XCD_AUTO) c.lat_chunk = c.reps.size() == 1 ? -1 : 0;
     else if (cfg->xcd_order == LB_XCD_HARDWARE) c.lat_chunk = 0;
     else if (cfg->xcd_order == LB_XCD_CONTIGUOUS) c.lat_chunk = -1;
@@ -996,8 +1007,20 @@ int lb_launch_shape(const lbmd_ctx* ctx, int* block, int* mapping, int* xcd_orde
     const Context& c = ctx->c;
     if (nt_stores) *nt_stores = c.lat_nt ? 1 : 0;
     if (block) *block = c.lat.block;
-    if (mapping) *mapping = c.lat.mapping == 1 ? LB_MAP_ROWS : c.lat.mapping == 2 ? LB_MAP_SHIFTED : LB_MAP_FLAT;
+    if (mapping)
+        *mapping = c.lat.mapping == 1   ? LB_MAP_ROWS
+                   : c.lat.mapping == 2 ? LB_MAP_SHIFTED
+                   : c.lat.mapping == 3 ? LB_MAP_FLAT2
+                                        : LB_MAP_FLAT;
     if (xcd_order) *xcd_order = c.lat_chunk < 0 ? LB_XCD_CONTIGUOUS : (c.lat_chunk == 0 ? LB_XCD_HARDWARE : c.lat_chunk);
+    return LB_OK;
+}
+
+int lb_pattern_copy(lbmd_ctx* ctx, int alternate) {
+    if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+    Context& c = ctx->c;
+    HIP_TRY(launch_pattern(c, c.pops[c.cur], c.pops[1 - c.cur], c.stream));
+    if (alternate) c.cur = 1 - c.cur;
     return LB_OK;
 }
 

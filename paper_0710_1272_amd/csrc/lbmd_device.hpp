@@ -55,15 +55,23 @@ __host__ __device__ constexpr float scale_of(int p) { return p == 0 ? 2.0f : (p 
 template <int S>
 struct Codec;
 
+// load/store: the population (full, or its deviation from w_p rho0).  load_raw/store_raw: the
+// stored number as such (16-bit: the scaled deviation s_p (f_p - w_p rho0)), which the lattice
+// kernel collides in directly with the scales folded into its constants; kScale<P> is the
+// factor between the two (1 for full storage).
 template <>
 struct Codec<LB_STORE_F64> {
     using T = double;
     using R = double;
     static constexpr bool deviation = false;
     template <int P>
+    static constexpr R kScale = 1.0;
+    template <int P>
     __device__ static R load(T v) { return v; }
     template <int P>
     __device__ static T store(R v) { return v; }
+    __device__ static R load_raw(T v) { return v; }
+    __device__ static T store_raw(R v) { return v; }
 };
 
 template <>
@@ -72,9 +80,13 @@ struct Codec<LB_STORE_F32> {
     using R = float;
     static constexpr bool deviation = false;
     template <int P>
+    static constexpr R kScale = 1.0f;
+    template <int P>
     __device__ static R load(T v) { return v; }
     template <int P>
     __device__ static T store(R v) { return v; }
+    __device__ static R load_raw(T v) { return v; }
+    __device__ static T store_raw(R v) { return v; }
 };
 
 template <>
@@ -83,9 +95,13 @@ struct Codec<LB_STORE_F16DEV> {
     using R = float;
     static constexpr bool deviation = true;
     template <int P>
+    static constexpr R kScale = scale_of(P);
+    template <int P>
     __device__ static R load(T v) { return (float)v * (1.0f / scale_of(P)); }
     template <int P>
     __device__ static T store(R v) { return (_Float16)(v * scale_of(P)); }  // IEEE round-to-nearest-even
+    __device__ static R load_raw(T v) { return (float)v; }
+    __device__ static T store_raw(R v) { return (_Float16)v; }
 };
 
 template <>
@@ -94,17 +110,14 @@ struct Codec<LB_STORE_BF16DEV> {
     using R = float;
     static constexpr bool deviation = true;
     template <int P>
-    __device__ static R load(T v) {
-        return __builtin_bit_cast(float, (uint32_t)v << 16) * (1.0f / scale_of(P));
-    }
+    static constexpr R kScale = scale_of(P);
+    __device__ static R load_raw(T v) { return __builtin_bit_cast(float, (uint32_t)v << 16); }
+    // round to nearest even (one hardware conversion on gfx950); NaN stays a quiet NaN
+    __device__ static T store_raw(R v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
     template <int P>
-    __device__ static T store(R v) {
-        // round to nearest even on the upper 16 bits; NaN kept quiet
-        uint32_t b = __builtin_bit_cast(uint32_t, v * scale_of(P));
-        if ((b & 0x7fffffffu) > 0x7f800000u) return (T)0x7fc0u;
-        b += 0x7fffu + ((b >> 16) & 1u);
-        return (T)(b >> 16);
-    }
+    __device__ static R load(T v) { return load_raw(v) * (1.0f / scale_of(P)); }
+    template <int P>
+    __device__ static T store(R v) { return store_raw(v * scale_of(P)); }
 };
 
 // runtime-p wrappers (init / gather paths that are not performance critical)
@@ -212,13 +225,12 @@ __host__ __device__ __forceinline__ int mirror_combo(bool fx, bool fy, bool fz) 
     return fx ? (fy ? (fz ? mxyz : mxy) : (fz ? mxz : mx)) : (fy ? (fz ? myz : my) : (fz ? mz : P));
 }
 
-// Pull resolver for a fluid node (x,y,z) and population P: where the value that
-// arrives in slot (x,P) was stored after the previous collision.  Source s = x - c_P;
-// a periodic axis wraps; a free-slip axis keeps x_a and reflects component a;
-// a solid source means the population bounced back: slot (x, opp(P)).
-// Returns the node index within the replica; *q receives the population.
+// Face resolution of the pull source of population P at node (x,y,z): s = x - c_P; a periodic
+// axis wraps, a free-slip axis keeps x_a and reflects component a.  No solidity test.  Returns
+// the node index within the replica, its coordinates in sc[3] and the population stored there
+// in *q.
 template <int P>
-__host__ __device__ __forceinline__ int pull_source(const Replica& R, int x, int y, int z, int* q) {
+__host__ __device__ __forceinline__ int pull_resolve(const Replica& R, int x, int y, int z, int* sc, int* q) {
     constexpr int cx = cx_of(P), cy = cy_of(P), cz = cz_of(P);
     int sx = x - cx, sy = y - cy, sz = z - cz;
     bool fx = false, fy = false, fz = false;
@@ -240,21 +252,34 @@ __host__ __device__ __forceinline__ int pull_source(const Replica& R, int x, int
             else sz += sz < 0 ? R.nz : -R.nz;
         }
     }
-    int qq = mirror_combo<P>(fx, fy, fz);
-    if (is_solid(R, sx, sy, sz)) {
-        sx = x;
-        sy = y;
-        sz = z;
-        qq = opp_of(P);
-    }
-    *q = qq;
+    *q = mirror_combo<P>(fx, fy, fz);
+    sc[0] = sx;
+    sc[1] = sy;
+    sc[2] = sz;
     return sx + R.nx * (sy + R.ny * sz);
 }
 
-// Push resolver (inverse of pull_source): where population Q leaving fluid node s
-// ends up.  Used to build a post-collision buffer whose pull gives wanted populations.
+// Pull resolver for a fluid node (x,y,z) and population P: where the value that
+// arrives in slot (x,P) was stored after the previous collision.  The face-resolved
+// source, or, when that source is solid, slot (x, opp(P)): the population bounced back.
+// Returns the node index within the replica; *q receives the population.
+template <int P>
+__host__ __device__ __forceinline__ int pull_source(const Replica& R, int x, int y, int z, int* q) {
+    int sc[3];
+    const int s = pull_resolve<P>(R, x, y, z, sc, q);
+    if (is_solid(R, sc[0], sc[1], sc[2])) {
+        *q = opp_of(P);
+        return x + R.nx * (y + R.ny * z);
+    }
+    return s;
+}
+
+// Face resolution of the push target of population QP leaving node (sx,sy,sz), the inverse of
+// pull_resolve: t = s + c_QP, a periodic axis wraps, a free-slip axis keeps s_a and reflects
+// component a.  No solidity test.  Returns the node index, its coordinates in tc[3] and the
+// population that arrives there in *p.
 template <int QP>
-__host__ __device__ __forceinline__ int push_target(const Replica& R, int sx, int sy, int sz, int* p) {
+__host__ __device__ __forceinline__ int push_resolve(const Replica& R, int sx, int sy, int sz, int* tc, int* p) {
     constexpr int cx = cx_of(QP), cy = cy_of(QP), cz = cz_of(QP);
     int tx = sx + cx, ty = sy + cy, tz = sz + cz;
     bool fx = false, fy = false, fz = false;
@@ -276,15 +301,25 @@ __host__ __device__ __forceinline__ int push_target(const Replica& R, int sx, in
             else tz += tz < 0 ? R.nz : -R.nz;
         }
     }
-    int pp = mirror_combo<QP>(fx, fy, fz);
-    if (is_solid(R, tx, ty, tz)) {
-        tx = sx;
-        ty = sy;
-        tz = sz;
-        pp = opp_of(QP);
-    }
-    *p = pp;
+    *p = mirror_combo<QP>(fx, fy, fz);
+    tc[0] = tx;
+    tc[1] = ty;
+    tc[2] = tz;
     return tx + R.nx * (ty + R.ny * tz);
+}
+
+// Push resolver (inverse of pull_source): where population Q leaving fluid node s
+// ends up, bounced back into (s, opp(Q)) when the face-resolved target is solid.  Used to
+// build a post-collision buffer whose pull gives wanted populations.
+template <int QP>
+__host__ __device__ __forceinline__ int push_target(const Replica& R, int sx, int sy, int sz, int* p) {
+    int tc[3];
+    const int t = push_resolve<QP>(R, sx, sy, sz, tc, p);
+    if (is_solid(R, tc[0], tc[1], tc[2])) {
+        *p = opp_of(QP);
+        return sx + R.nx * (sy + R.ny * sz);
+    }
+    return t;
 }
 
 // ---------------------------------------------------------------------------------
@@ -355,7 +390,7 @@ struct BeadPtrs {
     double* obs;        // [n_replicas][obs_cap + 1][8] observable record (header row first)
     // deterministic trilinear spread: open-addressing table of the nodes the stencils touch
     unsigned long long* hkey;  // [hcap] element offset of the node's population 0, plus 1 (0: empty)
-    int* hV;                   // [hcap] population stride (V) of the node's replica
+    int* hrep;                 // [hcap] replica of the node
     long long* hsum;           // [18][hcap] fixed-point sums of the moving populations' sources
     unsigned hcap;             // power of two, or 0 without the trilinear stencil
     int obs_every, obs_cap;

@@ -37,7 +37,8 @@ enum StepMode : int { STEP_LB = 0, STEP_COUPLED = 1, STEP_NO_HYDRO = 2 };
 // Lattice-kernel launch description for one block size.
 struct LatticeLaunch {
     int block = 0;
-    int mapping = 0;          // 0: 64 consecutive nodes per wave; 1: one row segment per wave
+    int mapping = 0;          // 0: 64 consecutive nodes per wave; 1: one row segment per wave;
+                              // 2: as 0 with x-rows rotated; 3: two nodes per lane, 64 apart
     int total_tiles = 0;
     int* d_prefix = nullptr;  // [n_reps + 1] first block of each replica (one row segment per wave)
 };
@@ -104,7 +105,7 @@ WorkLayout work_layout(int n_reps, int max_V, long long max_stage_nodes);
 // bead-buffer layout
 struct BeadLayout {
     size_t r, v, u, fbar, node, bond_next, agg_at, agg_f, rep_of, diag, nlist, ncount, rref, rs, obs;
-    size_t hkey, hV, hsum, total;
+    size_t hkey, hrep, hsum, total;
     unsigned hcap;
 };
 // obs_rows: rows of the observable record per replica (capacity + 1 header row; 0 = none);
@@ -114,6 +115,8 @@ BeadLayout bead_layout(int ntot, int n_reps, size_t real_size, int obs_rows, boo
 // kernel launchers (lb_kernels.hip / md_kernels.hip); all enqueue on `s`
 hipError_t launch_stream_collide(const Context& c, const void* src, void* dst, bool bump_step,
                                  hipStream_t s);
+// the same-pattern reference of the lattice kernel (current launch shape): src -> dst
+hipError_t launch_pattern(const Context& c, const void* src, void* dst, hipStream_t s);
 hipError_t launch_init(const Context& c, int r, void* dst, const double* d_rho, const double* d_u,
                        const double* d_pops, hipStream_t s);
 hipError_t launch_gather(const Context& c, int r, const void* src, int mode, long long node0,

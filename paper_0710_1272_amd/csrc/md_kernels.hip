@@ -1473,7 +1473,7 @@ __global__ __launch_bounds__(64) void k_spread_tri_fx(const Replica* __restrict_
         bool found = false;
         for (unsigned t = 0; t <= mask; ++t) {
             const unsigned long long old = atomicCAS(&b.hkey[h], 0ull, key);
-            if (old == 0ull) b.hV[h] = R.V;  // this thread opened the entry
+            if (old == 0ull) b.hrep[h] = b.rep_of[i];  // this thread opened the entry
             if (old == 0ull || old == key) {
                 found = true;
                 break;
@@ -1508,7 +1508,8 @@ __global__ __launch_bounds__(64) void k_spread_tri_fx(const Replica* __restrict_
 // populations of its node (each node has one entry, so plain read-modify-writes) and empties
 // the entry for the next step.
 template <int S>
-__global__ __launch_bounds__(256) void k_spread_fx_apply(BeadPtrs<typename MDReal<S>::type> b,
+__global__ __launch_bounds__(256) void k_spread_fx_apply(const Replica* __restrict__ reps,
+                                                         BeadPtrs<typename MDReal<S>::type> b,
                                                          typename Codec<S>::T* __restrict__ dst, RunState* st,
                                                          int bump_step) {
     using C = Codec<S>;
@@ -1518,7 +1519,7 @@ __global__ __launch_bounds__(256) void k_spread_fx_apply(BeadPtrs<typename MDRea
     if (h >= b.hcap) return;
     const unsigned long long key = b.hkey[h];
     if (key == 0ull) return;
-    const long long V = b.hV[h];
+    const long long V = reps[b.hrep[h]].V;
     typename C::T* __restrict__ base = dst + (long long)(key - 1ull);
     md_for_pops([&](auto P) {
         constexpr int p = decltype(P)::value;
@@ -1712,7 +1713,7 @@ static hipError_t launch_spread_fx_t(const Context& c, void* dst, bool bump, hip
     hipLaunchKernelGGL((k_spread_tri_fx<Real>), dim3(grid > 0 ? grid : 1), dim3(64), 0, s, c.d_reps, b, c.d_state);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_spread_fx_apply<S>), dim3((b.hcap + 255) / 256), dim3(256), 0, s, b,
+    hipLaunchKernelGGL((k_spread_fx_apply<S>), dim3((b.hcap + 255) / 256), dim3(256), 0, s, c.d_reps, b,
                        (typename Codec<S>::T*)dst, c.d_state, bump ? 1 : 0);
     return hipGetLastError();
 }

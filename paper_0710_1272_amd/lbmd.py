@@ -21,7 +21,7 @@ LB_BC_PERIODIC, LB_BC_FREESLIP = 0, 1
 LB_STORE_F64, LB_STORE_F32, LB_STORE_F16DEV, LB_STORE_BF16DEV = 0, 1, 2, 3
 LB_MAX_WALLS = 2
 LB_CFG_NO_GRAPH, LB_CFG_AUTOTUNE, LB_CFG_DETERMINISTIC = 1, 2, 4
-LB_MAP_AUTO, LB_MAP_FLAT, LB_MAP_ROWS, LB_MAP_SHIFTED = 0, 1, 2, 3
+LB_MAP_AUTO, LB_MAP_FLAT, LB_MAP_ROWS, LB_MAP_SHIFTED, LB_MAP_FLAT2 = 0, 1, 2, 3, 4
 LB_XCD_AUTO, LB_XCD_HARDWARE, LB_XCD_CONTIGUOUS = 0, -1, -2
 LB_BUF_POPS, LB_BUF_BEADS, LB_BUF_WORK = 0, 1, 2
 LB_STEP_COUPLED, LB_STEP_NO_HYDRO = 1, 2
@@ -37,7 +37,7 @@ LB_STENCIL_NGP, LB_STENCIL_TRILINEAR = 0, 1
 
 EXPORTED = ["lb_required_bytes", "lb_validate_config", "lb_init", "lb_step", "lb_graph_prepare", "lb_couple", "md_step",
             "lb_moments", "lb_moments_bytes", "lb_moments_range", "lb_block_size", "lb_launch_shape", "lb_md_lanes", "lb_destroy",
-            "lb_strerror", "lb_last_error_message", "lb_conserved_noalloc"]
+            "lb_strerror", "lb_last_error_message", "lb_conserved_noalloc", "lb_pattern_copy"]
 
 
 class lbmd_wall(C.Structure):
@@ -114,6 +114,7 @@ def lib():
         L.lb_launch_shape.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                       C.POINTER(C.c_int)]
         L.lb_md_lanes.argtypes = [C.c_void_p]
+        L.lb_pattern_copy.argtypes = [C.c_void_p, C.c_int]
         L.lb_conserved_noalloc.argtypes = [C.c_void_p, C.c_int, C.POINTER(lbmd_replica), C.c_void_p, C.c_void_p]
         L.lb_destroy.argtypes = [C.c_void_p]
         L.lb_strerror.argtypes = [C.c_int]
@@ -267,9 +268,14 @@ class Simulation:
         b, m, x, nt = C.c_int(), C.c_int(), C.c_int(), C.c_int()
         _check(lib().lb_launch_shape(self.ctx, C.byref(b), C.byref(m), C.byref(x), C.byref(nt)),
                "lb_launch_shape")
-        names = {LB_MAP_FLAT: "flat", LB_MAP_ROWS: "rows", LB_MAP_SHIFTED: "shifted"}
+        names = {LB_MAP_FLAT: "flat", LB_MAP_ROWS: "rows", LB_MAP_SHIFTED: "shifted", LB_MAP_FLAT2: "flat2"}
         return {"block": b.value, "mapping": names[m.value],
                 "xcd_order": x.value, "nt_stores": bool(nt.value), "md_lanes": self.md_lanes}
+
+    def pattern_copy(self, alternate: bool = False):
+        """One same-pattern reference launch of the lattice kernel (lb_pattern_copy); with
+        alternate, the copy becomes the current state (the populations lose their meaning)."""
+        _check(lib().lb_pattern_copy(self.ctx, 1 if alternate else 0), "lb_pattern_copy")
 
     @property
     def md_lanes(self) -> int:

@@ -89,7 +89,15 @@ def test_other_invalid_configs():
     assert _cfg([_rep()], with_beads=False).validate() == B.LB_EINVAL  # beads need positions
     assert _cfg([_rep()], block_size=96).validate() == B.LB_EINVAL
     assert _cfg([_rep()], mapping=B.LB_MAP_SHIFTED).validate() == B.LB_OK
-    assert _cfg([_rep()], mapping=B.LB_MAP_SHIFTED + 1).validate() == B.LB_EINVAL
+    assert _cfg([_rep()], mapping=B.LB_MAP_FLAT2).validate() == B.LB_OK
+    assert _cfg([_rep()], mapping=B.LB_MAP_FLAT2, block_size=64).validate() == B.LB_EINVAL
+    assert _cfg([_rep()], mapping=B.LB_MAP_FLAT2 + 1).validate() == B.LB_EINVAL
+    # one population of a replica is addressed with 32-bit byte offsets: at most 4 GiB
+    big = [Replica(Box(1024, 1024, 512, (PERIODIC,) * 3), [], 1)]  # 2^29 nodes
+    assert _cfg(big, storage=B.LB_STORE_F64, with_beads=False).validate() == B.LB_OK
+    bigger = [Replica(Box(1024, 1024, 513, (PERIODIC,) * 3), [], 1)]
+    assert _cfg(bigger, storage=B.LB_STORE_F64, with_beads=False).validate() == B.LB_EINVAL
+    assert _cfg(bigger, storage=B.LB_STORE_F32, with_beads=False).validate() == B.LB_OK
     assert _cfg([_rep()], mapping=-1).validate() == B.LB_EINVAL
     box = Box(8, 8, 8, (PERIODIC,) * 3)
     assert _cfg([Replica(box, [], 0)], with_beads=False).validate() == B.LB_OK

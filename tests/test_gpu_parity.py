@@ -56,13 +56,15 @@ BOXES = [
 ]
 
 
-MAPPINGS = {"flat": 1, "rows": 2, "shifted": 3}  # LB_MAP_FLAT, LB_MAP_ROWS, LB_MAP_SHIFTED
+MAPPINGS = {"flat": 1, "rows": 2, "shifted": 3, "flat2": 4}  # LB_MAP_FLAT, _ROWS, _SHIFTED, _FLAT2
 
 
 @pytest.mark.parametrize("mapping", list(MAPPINGS))
 @pytest.mark.parametrize("block", [64, 256, 1024])
 @pytest.mark.parametrize("bi", range(len(BOXES)))
 def test_boundaries_fp64(bi, block, mapping):
+    if mapping == "flat2" and block in (64, 1024):
+        block = 128 if block == 64 else 512  # two nodes per lane run blocks of 128-512 threads
     box = BOXES[bi]
     rep = Replica(box, [], 3)
     rho, u = G.random_small_flow(box, seed=bi)
@@ -84,13 +86,78 @@ def test_mappings_identical(storage):
     rep = Replica(w.replicas[0].box, [], w.replicas[0].seed)
     rho, u = G.random_small_flow(rep.box, seed=5, du=0.02)
     out = {}
-    for name, m in MAPPINGS.items():
+    maps = MAPPINGS
+    for name, m in maps.items():
         log(f"mappings identical {WC.STORE_NAMES[storage]} mapping={name}")
         with gpu_sim([rep], w.md, storage, rho, u, mapping=m) as sim:
+            assert sim.launch_shape()["mapping"] == name
             sim.step(20, coupled=False)
             out[name] = sim.populations()
-    assert np.array_equal(out["rows"], out["flat"])
-    assert np.array_equal(out["shifted"], out["flat"])
+    for name in maps:
+        assert np.array_equal(out[name], out["flat"]), name
+
+
+@pytest.mark.parametrize("storage", [F16, BF16], ids=["f16dev", "bf16dev"])
+@pytest.mark.parametrize("mapping", list(MAPPINGS))
+@pytest.mark.parametrize("bi", range(len(BOXES)))
+def test_boundaries_16bit(bi, mapping, storage):
+    """16-bit storage on every boundary geometry (walls with pores, periodic and free-slip x
+    faces, y/z faces): every mapping gives the same bits, and the velocity field stays within
+    the 16-bit bar of the oracle's after 30 steps."""
+    box = BOXES[bi]
+    rep = Replica(box, [], 3)
+    rho, u = G.random_small_flow(box, seed=bi)
+    out = {}
+    for name in (mapping, "flat"):
+        with gpu_sim([rep], MDParams(), storage, rho, u, block_size=128, mapping=MAPPINGS[name]) as sim:
+            sim.step(30, coupled=False)
+            out[name] = (sim.populations(), sim.fields()[1])
+    assert np.array_equal(out[mapping][0], out["flat"][0])
+    ora = oracle_sim(rep, MDParams(), rho, u)
+    ora.step(30, coupled=False)
+    _, uo = O.fields(box, ora.f)
+    fl = _fluid(box)
+    e = float(np.max(np.abs(out[mapping][1][:, fl] - uo[:, fl])) / np.max(np.abs(uo[:, fl])))
+    log(f"  box {bi} {mapping} {WC.STORE_NAMES[storage]}: velocity error / max|u| {e:.2e}")
+    assert e < (1e-3 if storage == F16 else 2e-2)
+
+
+@pytest.mark.parametrize("storage,mapping", [(F32, 1), (F16, 4), (F16, 2)], ids=["f32", "f16-flat2", "f16-rows"])
+def test_pattern_copy_leaves_the_state(storage, mapping):
+    """lb_pattern_copy (the same-pattern reference launch) overwrites only the buffer the next
+    update rewrites: coupled steps around it give the bits of steps without it."""
+    w = WC.c2_translocation(storage)
+    rep = w.replicas[0]
+    beads = G.replica_beads(rep, w.md)
+    res = []
+    for copy in (False, True):
+        with gpu_sim([rep], w.md, storage, beads=beads, mapping=mapping) as sim:
+            sim.step(5)
+            if copy:
+                sim.pattern_copy()
+                sim.pattern_copy()
+            sim.step(5)
+            res.append((sim.populations(), sim.beads()[0]))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+
+
+def test_pattern_copy_alternating():
+    """lb_pattern_copy(alternate): the copy becomes the current state (the other buffer), so the
+    read-out changes and a second copy moves back to the first buffer; no error is raised."""
+    w = WC.c2_translocation(F32)
+    rep = WC.Replica(w.replicas[0].box, [], 0)
+    rho, u = G.random_small_flow(rep.box, 3, du=0.01)
+    with gpu_sim([rep], w.md, F32, rho, u) as sim:
+        f0 = sim.populations()
+        sim.pattern_copy(alternate=True)
+        f1 = sim.populations()
+        sim.pattern_copy(alternate=True)
+        sim.pattern_copy(alternate=False)
+        f2 = sim.populations()
+        assert sim.status()[0] == 0
+    assert not np.array_equal(f0, f1)
+    assert not np.array_equal(f1, f2) and np.all(np.isfinite(f2))
 
 
 def test_init_populations_roundtrip():
