@@ -157,8 +157,9 @@ typedef struct lbmd_config {
     int lattice_mapping;               /* LB_MAP_*: how lattice-kernel threads map to nodes */
     int xcd_order;                     /* LB_XCD_* or a chunk size > 0: tile order over the 8 XCDs */
     int md_lanes;                      /* lanes per bead in the bead kernel: 0 = by bead count,
-                                          1, or 2/4/8/16 with lanes x (beads of the largest
-                                          replica) <= 512; LB_CFG_AUTOTUNE times the choices */
+                                          1, 2 (up to 512 beads in the largest replica), or
+                                          4/8/16 with lanes x (beads of the largest replica)
+                                          <= 512; LB_CFG_AUTOTUNE times the choices */
     unsigned flags;                    /* LB_CFG_* */
     int obs_every;                     /* record the translocation observables (LB_MOM_OBSERVABLES)
                                           after every step whose new step count is a multiple of

@@ -416,16 +416,22 @@ __device__ __forceinline__ int build_list(int i, int n, bool bn, bool bp, const 
         }
         return total;
     } else {
-        // one pass: each lane marks its hits j = gl + m G (m < n / G <= 512 / G^2 <= 128)
-        // in a 128-bit mask, then the group places them by an exclusive prefix of counts
-        unsigned long long hit0 = 0ull, hit1 = 0ull;
+        // one pass: each lane marks its hits j = gl + m G in a mask of 64 W bits, then the
+        // group places them by an exclusive prefix of counts.  m < n / G: at most
+        // 512 / G^2 <= 128 for G >= 4 (lanes x beads <= 512) and 256 for G = 2 (up to 512
+        // beads)
+        constexpr int W = G == 2 ? 4 : 2;
+        unsigned long long hit[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) hit[w] = 0ull;
         int mine = 0, m = 0;
         for (int j = gl; j < n; j += G, ++m) {
             if (j == i || (j == i + 1 && bn) || (j == i - 1 && bp)) continue;
             Real d[3];
             if (separation<Real, PERIODIC>(ri, PX, PY, PZ, j, per, nd, d) < rl2) {
-                if (m < 64) hit0 |= 1ull << m;
-                else hit1 |= 1ull << (m - 64);
+                const unsigned long long bit = 1ull << (m & 63);
+#pragma unroll
+                for (int w = 0; w < W; ++w) hit[w] |= (m >> 6) == w ? bit : 0ull;
                 ++mine;
             }
         }
@@ -438,15 +444,14 @@ __device__ __forceinline__ int build_list(int i, int n, bool bn, bool bp, const 
         int pos = incl - mine;
         const int total = __shfl(incl, G - 1, G);
         if (total <= kNeighbourMax) {
-            while (hit0) {
-                const int b = __builtin_ctzll(hit0);
-                hit0 &= hit0 - 1;
-                list[(size_t)(pos++) * stride] = (unsigned short)(gl + b * G);
-            }
-            while (hit1) {
-                const int b = __builtin_ctzll(hit1);
-                hit1 &= hit1 - 1;
-                list[(size_t)(pos++) * stride] = (unsigned short)(gl + (64 + b) * G);
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                unsigned long long h = hit[w];
+                while (h) {
+                    const int b = __builtin_ctzll(h);
+                    h &= h - 1;
+                    list[(size_t)(pos++) * stride] = (unsigned short)(gl + (64 * w + b) * G);
+                }
             }
         }
         return total;
@@ -1595,7 +1600,8 @@ int md_default_lanes(int max_beads) {
 
 bool md_lanes_valid(int lanes, int max_beads) {
     if (lanes == 1) return max_beads <= 4096;
-    return (lanes == 2 || lanes == 4 || lanes == 8 || lanes == 16) && (long long)lanes * max_beads <= 512;
+    if (lanes == 2) return max_beads <= 512;
+    return (lanes == 4 || lanes == 8 || lanes == 16) && (long long)lanes * max_beads <= 512;
 }
 
 template <class Real, int G, int BPT, bool PER, int MAXT, bool POLY>
@@ -1636,7 +1642,11 @@ static hipError_t launch_md_g(const Context& c, const void* cur, int mode, hipSt
         case 16: return launch_md_t<Real, 16, 1, PER, 512, POLY>(c, cur, mode, blk(16 * m), s);
         case 8: return launch_md_t<Real, 8, 1, PER, 512, POLY>(c, cur, mode, blk(8 * m), s);
         case 4: return launch_md_t<Real, 4, 1, PER, 512, POLY>(c, cur, mode, blk(4 * m), s);
-        case 2: return launch_md_t<Real, 2, 1, PER, 512, POLY>(c, cur, mode, blk(2 * m), s);
+        case 2:
+            // two lanes per bead: up to 256 beads in the 512-thread bound, up to 512 in the
+            // 1024-thread one
+            if (2 * m <= 512) return launch_md_t<Real, 2, 1, PER, 512, POLY>(c, cur, mode, blk(2 * m), s);
+            return launch_md_t<Real, 2, 1, PER, 1024, POLY>(c, cur, mode, blk(2 * m), s);
         default: break;
     }
     if (m <= 512) return launch_md_t<Real, 1, 1, PER, 512, POLY>(c, cur, mode, blk(m), s);

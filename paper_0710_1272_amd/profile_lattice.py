@@ -1,4 +1,4 @@
-"""HBM traffic of the lattice kernel from rocprofv3 counters.
+"""Profiling runs of the lattice kernel and the coupled step (rocprofv3).
 
   run:        lattice-kernel launches (LB-only steps) on a named workload, then copies of
               a known number of bytes by a plain copy kernel, for one counter pass:
@@ -8,6 +8,12 @@
   summarize:  reads the two counter CSVs, scales each counter by what it reads for the
               copy (bytes moved / counter), and records bytes per lattice launch in
               profiles/traffic.json with the hash of the kernel source it was taken on.
+  trace:      coupled steps of a named workload in the benchmark's configuration (autotuned
+              launch shapes, graph launches, the workload's chains), for a kernel trace:
+                rocprofv3 --kernel-trace --stats --output-format csv -d D -o c3 -- \
+                    python3 -m paper_0710_1272_amd.profile_lattice trace --workload c3 --storage f32
+  trace-summary: per-kernel durations over the last --window dispatches of each kernel in a
+              kernel-trace CSV (the timed steps, after the autotuner's trials).
 """
 from __future__ import annotations
 
@@ -39,6 +45,8 @@ def workload(name: str, storage: str):
     from workloads import configs as WC
 
     st = {"f32": WC.STORE_F32, "f16dev": WC.STORE_F16, "bf16dev": WC.STORE_BF16}[storage]
+    if name == "c4":
+        return WC.c4_batched(256, st), st
     w = {"c2": WC.c2_translocation, "c3": WC.c3_translocation, "c5": WC.c5_large}[name](st)
     return w, st
 
@@ -51,7 +59,8 @@ def run(args):
 
     w, st = workload(args.workload, args.storage)
     reps = [WC.Replica(r.box, [], r.seed) for r in w.replicas]
-    mapping = {"flat": B.LB_MAP_FLAT, "rows": B.LB_MAP_ROWS, "shifted": B.LB_MAP_SHIFTED}[args.mapping]
+    mapping = {"flat": B.LB_MAP_FLAT, "rows": B.LB_MAP_ROWS, "shifted": B.LB_MAP_SHIFTED,
+               "flat2": B.LB_MAP_FLAT2}[args.mapping]
     sim = B.Simulation(reps, w.md, st, {}, mapping=mapping)
     for _ in range(LAUNCHES):
         sim.step(1, coupled=False)
@@ -64,6 +73,52 @@ def run(args):
     torch.cuda.synchronize()
     print(f"profile_lattice: {w.name} {args.storage}: {LAUNCHES} lattice launches, "
           f"{COPIES} copies of {COPY_BYTES} bytes", flush=True)
+
+
+def trace(args):
+    """Coupled steps in the benchmark's configuration, after a warm-up, in blocks of at most
+    100 graph-launched steps."""
+    import numpy as np
+    import torch
+
+    from paper_0710_1272_amd import lbmd as B
+    from workloads import generate as G
+
+    w, st = workload(args.workload, args.storage)
+    beads = np.concatenate([G.replica_beads(r, w.md) for r in w.replicas])
+    sim = B.Simulation(w.replicas, w.md, st, {"bead_r": beads}, flags=B.LB_CFG_AUTOTUNE)
+    sim.step(args.warmup)
+    done = 0
+    while done < args.steps:
+        k = min(100, args.steps - done)
+        sim.prepare(k)
+        sim.step(k)
+        sim.conserved()
+        done += k
+    torch.cuda.synchronize()
+    print(f"profile_lattice trace: {w.name} {args.storage}: {args.warmup} + {args.steps} coupled steps, "
+          f"launch shape {sim.launch_shape()}", flush=True)
+    sim.close()
+
+
+def trace_summary(args):
+    """Mean and median duration of each kernel's last `window` dispatches in a kernel-trace
+    CSV, and the spacing of the last dispatches of the most frequent kernel."""
+    rows = {}
+    with open(args.trace_csv) as fh:
+        for r in csv.DictReader(fh):
+            rows.setdefault(r["Kernel_Name"], []).append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    out = []
+    for name, ts in rows.items():
+        ts.sort()
+        last = ts[-args.window:]
+        d = sorted(e - b for b, e in last)
+        out.append((sum(d) / len(d), name, len(ts), len(last), d[len(d) // 2]))
+    out.sort(reverse=True)
+    print("| kernel | dispatches | last | mean ns (last) | median ns (last) |")
+    print("|---|---|---|---|---|")
+    for mean, name, n, k, med in out:
+        print(f"| `{name[:90]}` | {n} | {k} | {mean:.0f} | {med} |")
 
 
 def _per_dispatch(path, counter):
@@ -112,16 +167,19 @@ def summarize(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["run", "summarize"])
-    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c5"])
+    ap.add_argument("mode", choices=["run", "summarize", "trace", "trace-summary"])
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--storage", default="f32", choices=["f32", "f16dev", "bf16dev"])
-    ap.add_argument("--mapping", default="shifted", choices=["flat", "rows", "shifted"],
-                    help="thread-to-node mapping of the lattice launches (shifted is flat where "
-                         "no row rotation applies)")
+    ap.add_argument("--mapping", default="flat", choices=["flat", "rows", "shifted", "flat2"],
+                    help="thread-to-node mapping of the lattice launches in run mode")
+    ap.add_argument("--steps", type=int, default=100, help="timed coupled steps (trace)")
+    ap.add_argument("--warmup", type=int, default=20, help="coupled steps before them (trace)")
     ap.add_argument("--fetch-csv")
     ap.add_argument("--write-csv")
+    ap.add_argument("--trace-csv")
+    ap.add_argument("--window", type=int, default=100)
     args = ap.parse_args()
-    run(args) if args.mode == "run" else summarize(args)
+    {"run": run, "summarize": summarize, "trace": trace, "trace-summary": trace_summary}[args.mode](args)
 
 
 if __name__ == "__main__":

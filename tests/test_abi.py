@@ -126,6 +126,11 @@ def test_md_lanes_validation():
     assert _cfg(big, md_lanes=4).validate() == B.LB_OK
     assert _cfg(big, md_lanes=8).validate() == B.LB_EINVAL
     assert _cfg(big, md_lanes=1).validate() == B.LB_OK
+    # two lanes per bead up to 512 beads (the 1024-thread bound above 256)
+    mid = [Replica(_rep().box, [300], 1)]
+    assert _cfg(mid, md_lanes=2).validate() == B.LB_OK
+    assert _cfg(mid, md_lanes=4).validate() == B.LB_EINVAL
+    assert _cfg([Replica(_rep().box, [513], 1)], md_lanes=2).validate() == B.LB_EINVAL
 
 
 def test_trilinear_node_table_in_bead_buffer():

@@ -29,6 +29,8 @@ F64, F32 = WC.STORE_F64, WC.STORE_F32
 
 # (chain, crowders of 25): 700, 1000, 1600 and 2400 beads
 COUNTS = {700: (300, 16), 1000: (400, 24), 1600: (800, 32), 2400: (800, 64)}
+# two lanes per bead above 256 beads run in the 1024-thread bound
+TWO_LANE_COUNTS = {450: (200, 10)}
 
 
 def _box():
@@ -49,7 +51,7 @@ def _beads(box, chain, crowders, seed):
 
 @functools.lru_cache(maxsize=None)
 def _case(n):
-    chain, crowders = COUNTS[n]
+    chain, crowders = {**COUNTS, **TWO_LANE_COUNTS}[n]
     box = _box()
     rep = Replica(box, [chain] + [25] * crowders, 7000 + n)
     return rep, _beads(box, chain, crowders, 11 + n)
@@ -130,3 +132,53 @@ def test_large_replica_coupled_steps(n, storage, pop_tol, pos_tol):
     assert np.array_equal(node_g, ora.node)
     assert np.max(np.abs(fb_g - ora.fbar)) < 100 * pos_tol
     assert tr["n_t"] == O.transloc(rep.box, ora.r)[0]
+
+
+@pytest.mark.parametrize("storage,tol", [(F64, 1e-11), (F32, 2e-4)], ids=["f64", "f32"])
+def test_two_lanes_per_bead_1024_threads(storage, tol):
+    """Two lanes per bead for 450 beads (900 threads, the 1024-thread bound): INTERP +
+    md_step against the oracle, then 5 coupled steps against the oracle's populations and
+    beads."""
+    n = 450
+    rep, beads = _case(n)
+    box, md = rep.box, MDParams()
+    rho, u = G.random_small_flow(box, 9, du=0.01)
+    ora = oracle_sim(rep, md, rho, u, beads=beads, step0=11)
+    u_o, node_o = O.interp(box, ora.f, ora.r)
+    r_o, v_o = ora.r.copy(), ora.v.copy()
+    fbar_o, flags_o = O.md_substeps(box, md, rep.chain_len, r_o, v_o, u_o, 11, rep.seed)
+    from paper_0710_1272_amd import lbmd as B
+    with gpu_sim([rep], md, storage, rho, u, beads=beads, step0=11, md_lanes=2) as sim:
+        assert sim.md_lanes == 2
+        sim.couple(B.LB_COUPLE_INTERP)
+        sim.md_step()
+        r_g, v_g = sim.beads()
+        u_g, fb_g, node_g = sim.coupling()
+        word, _ = sim.status()
+    scale_v = max(1.0, np.max(np.abs(v_o)))
+    log(f"  {n} beads, two lanes each, {WC.STORE_NAMES[storage]}: |dr| {np.max(np.abs(r_g - r_o)):.2e} "
+        f"|dv| {np.max(np.abs(v_g - v_o)):.2e} |dFbar| {np.max(np.abs(fb_g - fbar_o)):.2e}")
+    assert word == flags_o == 0
+    assert np.array_equal(node_g, node_o)
+    assert np.max(np.abs(u_g - u_o)) < tol
+    assert np.max(np.abs(r_g - r_o)) < tol
+    assert np.max(np.abs(v_g - v_o)) < tol * scale_v
+    assert np.max(np.abs(fb_g - fbar_o)) < tol * scale_v
+
+    steps = 5
+    pop_tol, pos_tol = (1e-11, 1e-10) if storage == F64 else (1e-5, 1e-4)
+    ora = oracle_sim(rep, md, beads=beads)
+    with gpu_sim([rep], md, storage, beads=beads, md_lanes=2) as sim:
+        for k in range(steps):
+            ora.step(1)
+            sim.step(1)
+            assert np.array_equal(sim.coupling()[2], ora.node), f"a nearest-node decision differs at step {k + 1}"
+        f = sim.populations()
+        r, v = sim.beads()
+        err_word, _ = sim.status()
+    err = max_rel(f, ora.f, ~O.solid_mask(rep.box))
+    log(f"    {steps} coupled steps: populations max rel {err:.2e}; |dr| {np.max(np.abs(r - ora.r)):.2e}")
+    assert err_word == 0 and ora.flags == 0
+    assert err < pop_tol
+    assert np.max(np.abs(r - ora.r)) < pos_tol
+    assert np.max(np.abs(v - ora.v)) < 100 * pos_tol
