@@ -39,14 +39,20 @@ def log(msg):
 
 
 def cpu_model() -> str:
+    """The host CPU as /proc/cpuinfo names it, with its family / model / stepping numbers
+    (a virtual machine may report only the brand) and the logical CPUs visible."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if ":" in line:
+                    k, v = line.split(":", 1)
+                    info.setdefault(k.strip(), v.strip())
     except OSError:
         pass
-    return platform.processor() or "unknown"
+    name = info.get("model name") or platform.processor() or "unknown"
+    ids = [f"{k} {info[k]}" for k in ("cpu family", "model", "stepping") if k in info]
+    return f"{name} ({', '.join(ids + [f'{os.cpu_count()} logical CPUs visible'])})"
 
 
 def measured_traffic(workload: str, storage: str):

@@ -831,25 +831,51 @@ __global__ __launch_bounds__(256) void k_gather(const Replica* __restrict__ reps
     }
 }
 
-// FP64 totals of rho and j over the fluid nodes of replica r: per-thread sums over
-// a fixed grid-stride, wavefront butterfly, block tree, one partial per block; a
-// second single-block pass adds the partials in a fixed order (deterministic).
+// FP64 totals of rho and j over the fluid nodes of replica r (Eqs. dens, vel summed over the
+// box): per-lane sums over a fixed sequence of 64-node chunks, wavefront butterfly, block
+// tree, one partial per block; a second single-block pass adds the partials in a fixed order
+// (deterministic for a given grid).
 template <int S>
 __global__ __launch_bounds__(256) void k_conserved_partial(const Replica R,
                                                            const typename Codec<S>::T* __restrict__ src,
                                                            double* __restrict__ partials) {
+    using C = Codec<S>;
+    using Rl = typename C::R;
+    // 64 consecutive nodes per wave, dealt to the waves of the grid in a fixed order; each
+    // wave takes the cheapest gather that covers its lanes, as the lattice kernel does
     double acc[4] = {0, 0, 0, 0};
-    for (int s = blockIdx.x * 256 + threadIdx.x; s < R.V; s += gridDim.x * 256) {
-        const int x = s % R.nx, y = (s / R.nx) % R.ny, z = s / (R.nx * R.ny);
-        if (is_solid(R, x, y, z)) continue;
-        double f[Q];
-        gather_f64<S>(R, src, x, y, z, f);
+    const int lane = threadIdx.x & 63;
+    const long long chunks = (R.V + 63) / 64;
+    for (long long ch = blockIdx.x * 4LL + (threadIdx.x >> 6); ch < chunks; ch += gridDim.x * 4LL) {
+        const long long n = ch * 64 + lane;
+        const bool inside = n < R.V;
+        const int idx = inside ? (int)n : (int)(R.V - 1);
+        const uint32_t t = fdiv((uint32_t)idx, R.div_nx);
+        const int x = idx - (int)t * R.nx;
+        const uint32_t zz = fdiv(t, R.div_ny);
+        const int y = (int)t - (int)zz * R.ny;
+        const int z = (int)zz;
+        const bool fluid = inside && !is_solid(R, x, y, z);
+        const bool any_face = __ballot(fluid && (y == 0 || y == R.ny - 1 || z == 0 || z == R.nz - 1)) != 0;
+        const bool any_pore = __ballot(fluid && near_pore(R, x, y, z)) != 0;
+        const bool any_zone = __ballot(fluid && in_wall_zone(R, x)) != 0;
+        const bool any_xface = __ballot(fluid && (x == 0 || x == R.nx - 1)) != 0;
+        if (!fluid) continue;
+        Rl f[Q];
+        if (any_face) gather19<S, G_GENERIC>(R, src, idx, x, y, z, f);
+        else if (any_pore) gather19<S, G_WALL>(R, src, idx, x, y, z, f);
+        else if (any_zone) gather19<S, G_WALL_PLANE>(R, src, idx, x, y, z, f);
+        else if (any_xface) gather19<S, G_FAST>(R, src, idx, x, y, z, f);
+        else gather19<S, G_INTERIOR>(R, src, idx, x, y, z, f);
         for_pops([&](auto P) {
             constexpr int p = decltype(P)::value;
-            acc[0] += f[p];
-            acc[1] += cx_of(p) * f[p];
-            acc[2] += cy_of(p) * f[p];
-            acc[3] += cz_of(p) * f[p];
+            // the stored number decoded as Codec::load does, then the rest value added in FP64
+            double v = (double)(f[p] * (Rl(1) / C::template kScale<p>));
+            if constexpr (C::deviation) v += w_of<double>(p) * R.rho0;
+            acc[0] += v;
+            if constexpr (cx_of(p) != 0) acc[1] += cx_of(p) * v;
+            if constexpr (cy_of(p) != 0) acc[2] += cy_of(p) * v;
+            if constexpr (cz_of(p) != 0) acc[3] += cz_of(p) * v;
         });
     }
     __shared__ double red[4][256 / 64];

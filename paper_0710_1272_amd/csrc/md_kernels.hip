@@ -1438,8 +1438,11 @@ __global__ __launch_bounds__(256) void k_spread_tri(const Replica* __restrict__ 
 // Each contribution -w_c (w_p / c_s^2) Fbar . c_p is rounded once to a multiple of 2^-48
 // (in FP64) and added as a 64-bit integer into a table entry of its node; a second pass adds
 // each node's exact sums to its populations (one rounding each) and empties the entry.
+// A contribution is at most 2^9 in magnitude (larger ones are dropped and flagged), so a
+// node's signed 64-bit sum cannot overflow below 2^(63 - 48 - 9) = 64 contributions; a node
+// collects one from each bead whose 8-node stencil holds it, a handful at WCA densities.
 constexpr double kFxScale = 281474976710656.0;  // 2^48
-constexpr double kFxLimit = 16384.0;            // larger contributions are dropped and flagged
+constexpr double kFxLimit = 512.0;
 
 // slot of a key: the splitmix64 finaliser (Steele, Lea and Flood, OOPSLA 2014) as a hash
 __device__ __forceinline__ unsigned fx_hash(unsigned long long k, unsigned mask) {
