@@ -75,7 +75,12 @@ def test_boundaries_fp64(bi, block, mapping):
         assert sim.launch_shape()["mapping"] == mapping
         sim.step(30, coupled=False)
         f = sim.populations()
+        cons = sim.conserved()
     assert max_rel(f, ora.f, _fluid(box)) < 1e-12
+    # the FP64 conserved sums (their own gather per wave class) against the oracle's sums
+    c_o = O.conserved(box, ora.f)
+    assert abs(cons[0] - c_o[0]) < 1e-12 * c_o[0]
+    assert np.max(np.abs(cons[1:] - c_o[1:])) < 1e-12 * c_o[0]
 
 
 @pytest.mark.parametrize("storage", [F32, F16])
@@ -111,8 +116,13 @@ def test_boundaries_16bit(bi, mapping, storage):
     for name in (mapping, "flat"):
         with gpu_sim([rep], MDParams(), storage, rho, u, block_size=128, mapping=MAPPINGS[name]) as sim:
             sim.step(30, coupled=False)
-            out[name] = (sim.populations(), sim.fields()[1])
+            out[name] = (sim.populations(), sim.fields()[1], sim.conserved())
     assert np.array_equal(out[mapping][0], out["flat"][0])
+    # the conserved-sum kernel decodes the stored numbers as the population read-out does:
+    # its sums equal the oracle's sums of the read-out populations (FP64 summation order only)
+    c_r = O.conserved(box, out[mapping][0])
+    assert abs(out[mapping][2][0] - c_r[0]) < 1e-12 * c_r[0]
+    assert np.max(np.abs(out[mapping][2][1:] - c_r[1:])) < 1e-12 * c_r[0]
     ora = oracle_sim(rep, MDParams(), rho, u)
     ora.step(30, coupled=False)
     _, uo = O.fields(box, ora.f)
