@@ -511,19 +511,34 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
     Real v[BPT][3], u[BPT][3], fb[BPT][3];
     int node[BPT];
     bool own[BPT];
+    // the kept Verlet list's state (the positions it was built at, its length, whether it is
+    // valid) does not depend on this step's positions: with one bead per lane it is fetched in
+    // the same round trip as the bead state instead of after the interpolation
+    double* dg = a.b.diag + 8 * blockIdx.x;
+    const double kept = dg[7];
+    double pre_rref[BPT][3];
+    int pre_cnt[BPT];
 #pragma unroll
     for (int k = 0; k < BPT; ++k) {
         const int i = grp + k * NG;
         own[k] = i < n;
         node[k] = -1;
+        pre_cnt[k] = 0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) { r[k][c] = 0; v[k][c] = 0; u[k][c] = 0; fb[k][c] = 0; }
+        for (int c = 0; c < 3; ++c) { r[k][c] = 0; v[k][c] = 0; u[k][c] = 0; fb[k][c] = 0; pre_rref[k][c] = 0; }
         if (own[k]) {
             const int g = b0 + i;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 r[k][c] = a.b.r[c * NT + g];
                 v[k][c] = a.b.v[c * NT + g];
+            }
+            if constexpr (BPT == 1) {
+                if (kept != 0.0) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) pre_rref[k][c] = a.b.rref[c * NT + g];
+                    pre_cnt[k] = a.b.ncount[g];
+                }
             }
             if (gl == 0) {
 #pragma unroll
@@ -589,8 +604,7 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
     double rref[BPT][3];
     int cnt[BPT];
     int builds = 0;
-    double* dg = a.b.diag + 8 * blockIdx.x;
-    bool reuse = dg[7] != 0.0;
+    bool reuse = kept != 0.0;
     if (reuse) {
         int moved = 0;
 #pragma unroll
@@ -603,23 +617,38 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
             Real disp2 = 0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                rref[k][c] = a.b.rref[c * NT + gi];
+                rref[k][c] = BPT == 1 ? pre_rref[k][c] : a.b.rref[c * NT + gi];
                 const Real dd = (Real)(r[k][c] - rref[k][c]);
                 disp2 += dd * dd;
             }
             moved |= !(disp2 <= hs2);
-            cnt[k] = a.b.ncount[gi];
+            cnt[k] = BPT == 1 ? pre_cnt[k] : a.b.ncount[gi];
         }
         reuse = !__syncthreads_or(moved);
     }
     if (reuse) {
         if (a.list_in_lds) {
+            // the kept list into LDS, 8 entries a lane per round trip (a load and its LDS
+            // store per entry would make every entry a dependent round trip)
+            constexpr int U = 8;
 #pragma unroll
             for (int k = 0; k < BPT; ++k) {
                 const int i = grp + k * NG;
                 if (!own[k]) continue;
                 const int m = cnt[k] < kNeighbourMax ? cnt[k] : kNeighbourMax;
-                for (int q = gl; q < m; q += G) lists[i + q * lstride] = a.b.nlist[(size_t)q * NT + b0 + i];
+                for (int q0 = gl; q0 < m; q0 += U * G) {
+                    unsigned short e[U];
+#pragma unroll
+                    for (int t = 0; t < U; ++t) {
+                        const int q = q0 + t * G;
+                        e[t] = q < m ? a.b.nlist[(size_t)q * NT + b0 + i] : (unsigned short)0;
+                    }
+#pragma unroll
+                    for (int t = 0; t < U; ++t) {
+                        const int q = q0 + t * G;
+                        if (q < m) lists[i + q * lstride] = e[t];
+                    }
+                }
             }
         }
     } else {
