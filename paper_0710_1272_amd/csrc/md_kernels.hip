@@ -1373,31 +1373,40 @@ __device__ __forceinline__ void trilinear_axes(const Replica& R, const double* r
 template <class Real>
 __global__ __launch_bounds__(256) void k_interp_tri(const Replica* __restrict__ reps, BeadPtrs<Real> b,
                                                     const void* cur, int storage) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= b.ntot) return;
+    // eight lanes a bead, lane c of the group owning stencil node c: the 8 x 19 population
+    // reads of a bead are issued by 8 lanes at once instead of one after the other
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = t >> 3, c = t & 7;
+    if (i >= b.ntot) return;  // whole groups of eight leave together
     const int NT = b.ntot;
     const Replica& R = reps[b.rep_of[i]];
     const double r[3] = {b.r[i], b.r[NT + i], b.r[2 * NT + i]};
     int lo[3][2];
     double w1[3][2];
     trilinear_axes(R, r, lo, w1);
-    double u[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const int g[3] = {lo[0][c & 1], lo[1][(c >> 1) & 1], lo[2][(c >> 2) & 1]};
-        if (is_solid(R, g[0], g[1], g[2])) continue;
+    const int g[3] = {lo[0][c & 1], lo[1][(c >> 1) & 1], lo[2][(c >> 2) & 1]};
+    double part[3] = {0.0, 0.0, 0.0};
+    if (!is_solid(R, g[0], g[1], g[2])) {
         const double w = w1[0][c & 1] * w1[1][(c >> 1) & 1] * w1[2][(c >> 2) & 1];
         Real uc[3];
         node_velocity<Real>(storage, R, cur, g, uc);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) u[a] += w * (double)uc[a];
+        for (int a = 0; a < 3; ++a) part[a] = w * (double)uc[a];
     }
+    // the group's first lane adds the eight parts in stencil order (a solid node adds 0)
+    double u[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        b.u[a * NT + i] = (Real)u[a];
-        b.rs[a * NT + i] = r[a];
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) u[a] += __shfl(part[a], k, 8);
+    if (c == 0) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            b.u[a * NT + i] = (Real)u[a];
+            b.rs[a * NT + i] = r[a];
+        }
+        b.node[i] = -1;
     }
-    b.node[i] = -1;
 }
 
 // 16-bit deviation storage: add to one element by compare-and-swap on the 32-bit word that
@@ -1429,8 +1438,10 @@ __global__ __launch_bounds__(256) void k_spread_tri(const Replica* __restrict__ 
                                                     int bump_step) {
     using C = Codec<S>;
     using Rl = typename C::R;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (bump_step && i == 0) st->step += 1;
+    // eight lanes a bead, lane c adding to stencil node c
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = t >> 3, c = t & 7;
+    if (bump_step && t == 0) st->step += 1;
     if (i >= b.ntot) return;
     const int NT = b.ntot;
     const Replica& R = reps[b.rep_of[i]];
@@ -1440,9 +1451,9 @@ __global__ __launch_bounds__(256) void k_spread_tri(const Replica* __restrict__ 
     double w1[3][2];
     trilinear_axes(R, r, lo, w1);
     const long long V = R.V;
-    for (int c = 0; c < 8; ++c) {
+    {
         const int g[3] = {lo[0][c & 1], lo[1][(c >> 1) & 1], lo[2][(c >> 2) & 1]};
-        if (is_solid(R, g[0], g[1], g[2])) continue;
+        if (is_solid(R, g[0], g[1], g[2])) return;
         const Rl w = (Rl)(w1[0][c & 1] * w1[1][(c >> 1) & 1] * w1[2][(c >> 2) & 1]);
         typename C::T* base = dst + R.pop_base + g[0] + (long long)R.nx * (g[1] + (long long)R.ny * g[2]);
         md_for_pops([&](auto P) {
@@ -1723,8 +1734,8 @@ template <int S>
 static hipError_t launch_spread_tri_t(const Context& c, void* dst, bool bump, hipStream_t s) {
     using Real = typename MDReal<S>::type;
     const BeadPtrs<Real> b = *(const BeadPtrs<Real>*)c.bead_ptrs;
-    // 64 threads a block, as for the nearest-node spread
-    const int grid = (c.ntot_beads + 63) / 64;
+    // eight lanes a bead in 64-thread blocks, as for the nearest-node spread
+    const int grid = (8 * c.ntot_beads + 63) / 64;
     hipLaunchKernelGGL((k_spread_tri<S>), dim3(grid > 0 ? grid : 1), dim3(64), 0, s, c.d_reps, b,
                        (typename Codec<S>::T*)dst, c.d_state, bump ? 1 : 0);
     return hipGetLastError();
@@ -1733,9 +1744,9 @@ static hipError_t launch_spread_tri_t(const Context& c, void* dst, bool bump, hi
 template <class Real>
 static hipError_t launch_interp_tri_t(const Context& c, const void* cur, hipStream_t s) {
     const BeadPtrs<Real> b = *(const BeadPtrs<Real>*)c.bead_ptrs;
-    // 64 threads a block: each bead's 8 x 19 population reads may miss the caches, and
-    // more compute units keep more misses in flight
-    const int grid = (c.ntot_beads + 63) / 64;
+    // eight lanes a bead in 64-thread blocks: each bead's 8 x 19 population reads may miss
+    // the caches, and more compute units keep more misses in flight
+    const int grid = (8 * c.ntot_beads + 63) / 64;
     hipLaunchKernelGGL((k_interp_tri<Real>), dim3(grid > 0 ? grid : 1), dim3(64), 0, s, c.d_reps, b, cur,
                        c.storage);
     return hipGetLastError();

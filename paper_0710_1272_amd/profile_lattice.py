@@ -84,9 +84,12 @@ def trace(args):
     from paper_0710_1272_amd import lbmd as B
     from workloads import generate as G
 
+    import dataclasses
+
     w, st = workload(args.workload, args.storage)
-    beads = np.concatenate([G.replica_beads(r, w.md) for r in w.replicas])
-    sim = B.Simulation(w.replicas, w.md, st, {"bead_r": beads}, flags=B.LB_CFG_AUTOTUNE)
+    md = dataclasses.replace(w.md, stencil=1) if args.trilinear else w.md
+    beads = np.concatenate([G.replica_beads(r, md) for r in w.replicas])
+    sim = B.Simulation(w.replicas, md, st, {"bead_r": beads}, flags=B.LB_CFG_AUTOTUNE)
     sim.step(args.warmup)
     done = 0
     while done < args.steps:
@@ -174,6 +177,7 @@ def main():
                     help="thread-to-node mapping of the lattice launches in run mode")
     ap.add_argument("--steps", type=int, default=100, help="timed coupled steps (trace)")
     ap.add_argument("--warmup", type=int, default=20, help="coupled steps before them (trace)")
+    ap.add_argument("--trilinear", action="store_true", help="the trilinear stencil (trace)")
     ap.add_argument("--fetch-csv")
     ap.add_argument("--write-csv")
     ap.add_argument("--trace-csv")
