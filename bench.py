@@ -484,7 +484,10 @@ def main():
                    "md_substeps": w.md.M, "storage": "f32", "diag_every": DIAG_EVERY, "launch": shape,
                    "precision_note": "populations stored and collided in FP32; bead positions, the "
                                      "conserved sums and the centre of mass in FP64 (bead velocities and "
-                                     "forces FP32)"},
+                                     "forces FP32); beyond FP64 reductions, positions are FP64 because "
+                                     "they integrate 1e5-1e6 small increments, and the rigid-bond "
+                                     "multipliers and trilinear weights (options not used here) are "
+                                     "FP64 too"},
         "roofline": {"bound": "hbm", "kernel": "k_stream_collide",
                      "achieved": rl["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": rl["frac"], "traffic": traffic, "alg_bytes_per_launch": alg,

@@ -78,7 +78,9 @@ def test_coupled_steps_with_thermal_fluid(storage, pop_tol, pos_tol):
     assert np.max(np.abs(v - ora.v)) < 100 * pos_tol
 
 
-@pytest.mark.parametrize("storage,tol", [(F16, 1e-2), (BF16, 5e-2)], ids=["f16dev", "bf16dev"])
+# FP16 at the 1e-3 bar of the precision requirement (measured 2.5e-4); BF16, whose 8-bit
+# significand cannot reach that bar, at 1e-2 (measured 2.2e-3)
+@pytest.mark.parametrize("storage,tol", [(F16, 1e-3), (BF16, 1e-2)], ids=["f16dev", "bf16dev"])
 def test_thermal_source_in_16bit_storage(storage, tol):
     box = BOXES["pore"]
     rep = Replica(box, [], 99)
