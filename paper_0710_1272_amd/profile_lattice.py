@@ -61,7 +61,7 @@ def run(args):
     reps = [WC.Replica(r.box, [], r.seed) for r in w.replicas]
     mapping = {"flat": B.LB_MAP_FLAT, "rows": B.LB_MAP_ROWS, "shifted": B.LB_MAP_SHIFTED,
                "flat2": B.LB_MAP_FLAT2}[args.mapping]
-    sim = B.Simulation(reps, w.md, st, {}, mapping=mapping)
+    sim = B.Simulation(reps, w.md, st, {}, mapping=mapping, xcd_order=args.xcd)
     for _ in range(LAUNCHES):
         sim.step(1, coupled=False)
     torch.cuda.synchronize()
@@ -154,7 +154,7 @@ def summarize(args):
     entry = {"bytes_per_launch": round(fetch + write), "fetch_bytes": round(fetch),
              "write_bytes": round(write), "alg_bytes": 2 * alg, "fetch_over_alg": round(fetch / alg, 4),
              "write_over_alg": round(write / alg, 4), "fetch_scale": round(sf, 4),
-             "write_scale": round(sw, 4), "launches": len(lat_f), "mapping": args.mapping,
+             "write_scale": round(sw, 4), "launches": len(lat_f), "mapping": args.mapping, "xcd_order": args.xcd,
              "kernel_hash": kernel_source_hash()}
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -175,6 +175,9 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16dev", "bf16dev"])
     ap.add_argument("--mapping", default="flat", choices=["flat", "rows", "shifted", "flat2"],
                     help="thread-to-node mapping of the lattice launches in run mode")
+    ap.add_argument("--xcd", type=int, default=0,
+                    help="XCD tile order of the lattice launches in run mode (LB_XCD_*, or a chunk "
+                         "size > 0; the default lets the library choose)")
     ap.add_argument("--steps", type=int, default=100, help="timed coupled steps (trace)")
     ap.add_argument("--warmup", type=int, default=20, help="coupled steps before them (trace)")
     ap.add_argument("--trilinear", action="store_true", help="the trilinear stencil (trace)")
