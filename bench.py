@@ -225,6 +225,54 @@ def accuracy(workload, storage, steps=10, picks=None, batched=False):
             "steps": steps, "replicas_compared": len(picks), "error_word": int(err)}
 
 
+def large_box_16bit(storage, f32_step_s, steps=50):
+    """The 512^3 two-wall workload with 16-bit deviation storage: coupled MLUPS, speedup over
+    the FP32 headline step, the lattice roofline, and the error against FP64 storage of the
+    same inputs (a random small flow and the workload's chains) after 10 coupled steps, over
+    sampled z-slabs (bulk, both walls with their pores, the faces): the box is too large to
+    read back whole at FP64."""
+    import numpy as np
+    import torch
+
+    from workloads import configs as WC
+    from workloads import generate as G
+
+    w = WC.c5_large(storage)
+    log(f"workload {w.name} {WC.STORE_NAMES[storage]}")
+    sim = build_case(w, storage)
+    sim.step(10)
+    dt = time_steps(sim, steps)
+    e = {"mlups": round(w.fluid_nodes * steps / dt / 1e6, 1), "ms_per_step": round(dt / steps * 1e3, 4),
+         "speedup_vs_f32": round(f32_step_s / (dt / steps), 3)}
+    e["lattice"] = lattice_roofline(sim, w.fluid_nodes, storage, n=16)
+    e["launch"] = sim.launch_shape()
+    sim.close()
+    torch.cuda.empty_cache()
+    # accuracy against FP64 storage on sampled slabs of 4 z-planes
+    rep = w.replicas[0]
+    box = rep.box
+    rho, u = G.random_small_flow(box, 700, du=0.01)
+    beads = G.replica_beads(rep, w.md)
+    nxy = box.nx * box.ny
+    slabs = [0, box.nz // 4, box.nz // 2 - 2, box.nz - 4]
+    res = {}
+    for st in (storage, WC.STORE_F64):
+        s2 = build_case(w, st, beads=False, flags=0, init={"rho": rho, "u": u.ravel(), "bead_r": beads})
+        s2.step(10)
+        res[st] = ([s2.fields_range(z * nxy, 4 * nxy) for z in slabs], s2.beads()[0], s2.status()[0])
+        s2.close()
+        torch.cuda.empty_cache()
+    ve = 0.0
+    for (rho_s, u_s), (rho_d, u_d) in zip(res[storage][0], res[WC.STORE_F64][0]):
+        fl = rho_d > 0
+        ve = max(ve, float(np.max(np.abs(u_s[:, fl] - u_d[:, fl])) / np.max(np.abs(u_d[:, fl]))))
+    e["accuracy_vs_f64"] = {"vel_err_over_max_u": float(f"{ve:.3g}"),
+                            "bead_drift_max": float(f"{np.max(np.abs(res[storage][1] - res[WC.STORE_F64][1])):.3g}"),
+                            "steps": 10, "sample": f"z-slabs of 4 planes at z = {slabs} (all x, y)",
+                            "error_word": int(res[storage][2] | res[WC.STORE_F64][2])}
+    return e
+
+
 def translocation_times(storage, n=512, cap=4000, check=250):
     """Completion steps of n independent translocation events (48^3 pore boxes, N = 32) run
     as one batch: mean and standard error of the completed ones."""
@@ -316,7 +364,7 @@ def storage_set(workload, steps, out, key, with_roofline=True, acc_kw=None):
         torch.cuda.empty_cache()
 
 
-def extra_workloads():
+def extra_workloads(f32_step_s):
     """The other configurations: 128x64x64 and 256x128x128 in FP32/FP16/BF16, the 256-replica
     batch against the same replicas one at a time in FP32, the paper's rigid chain, the
     thermal fluid, the no-solvent comparison and translocation times per storage format."""
@@ -328,6 +376,7 @@ def extra_workloads():
     from workloads import configs as WC
 
     out = {}
+    out["large512_two_walls:f16dev"] = large_box_16bit(WC.STORE_F16, f32_step_s)
     storage_set(WC.c2_translocation(WC.STORE_F32), 1000, out, "pore128x64x64_n100")
     storage_set(WC.c3_translocation(WC.STORE_F32), 300, out, "pore256x128x128_n400")
 
@@ -503,7 +552,7 @@ def main():
         "paper_context": "0.262 MLUPS coupled (N=100, 80x40x40 box) on a serial 2 GHz Opteron",
     }
     if not args.no_extras:
-        out["workloads"] = extra_workloads()
+        out["workloads"] = extra_workloads(step_s)
         out["no_solvent"] = no_hydro()
         tt = {}
         for st in (WC.STORE_F64, WC.STORE_F32, WC.STORE_F16, WC.STORE_BF16):
