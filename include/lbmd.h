@@ -144,8 +144,9 @@ typedef struct lbmd_initial_state {
                                    floating-point atomic adds whose order varies; and LB_CFG_AUTOTUNE
                                    leaves the lanes per bead at their choice by bead count, since
                                    they set the order of the bead-force sums.  The lattice kernel's
-                                   launch shape never changes results.  A contribution above 16384
-                                   in magnitude is dropped and sets LB_ERR_NONFINITE */
+                                   launch shape never changes results.  A contribution above 512
+                                   in magnitude is dropped and sets LB_ERR_NONFINITE (so that no
+                                   node's 64-bit sum can overflow below 64 contributions) */
 
 typedef struct lbmd_config {
     int n_replicas;
@@ -168,7 +169,7 @@ typedef struct lbmd_config {
 } lbmd_config;
 
 /* lattice_mapping */
-#define LB_MAP_AUTO 0  /* flat (LB_CFG_AUTOTUNE also tries rows and shifted) */
+#define LB_MAP_AUTO 0  /* flat (LB_CFG_AUTOTUNE also tries rows, shifted and flat2) */
 #define LB_MAP_FLAT 1  /* each wave takes 64 consecutive nodes of a replica */
 #define LB_MAP_ROWS 2  /* each wave takes one segment of at most 64 nodes of one x-row */
 #define LB_MAP_SHIFTED 3 /* flat, with each x-row rotated by whole 128-byte lines so that
@@ -320,7 +321,7 @@ int lb_conserved_noalloc(const void* pops, int storage, const lbmd_replica* rep,
 /* Lattice-kernel launch shape in use (threads per block). */
 int lb_block_size(const lbmd_ctx* ctx);
 
-/* Lattice-kernel launch shape in use: threads per block, LB_MAP_FLAT/ROWS/SHIFTED, the XCD
+/* Lattice-kernel launch shape in use: threads per block, LB_MAP_FLAT/ROWS/SHIFTED/FLAT2, the XCD
  * tile order (LB_XCD_HARDWARE, LB_XCD_CONTIGUOUS or a chunk size) and whether the
  * populations are written with non-temporal stores (1: both buffers together exceed
  * 160 MB, so they are streamed past the last-level cache; 0: they stay cached between
