@@ -170,6 +170,35 @@ def test_pattern_copy_alternating():
     assert not np.array_equal(f1, f2) and np.all(np.isfinite(f2))
 
 
+@pytest.mark.parametrize("storage", [F32, F16], ids=["f32", "f16dev"])
+@pytest.mark.parametrize("mapping", list(MAPPINGS))
+def test_solid_slots_hold_rest_values(mapping, storage):
+    """Every sweep writes the slots of solid nodes too (with w_p rho0, as lb_init does), so
+    that each store instruction of a wave covers whole cache lines: after two lattice steps,
+    one into each buffer, both raw population buffers hold the rest value at every solid
+    node (FP32: w_p rho0; 16-bit deviation storage: 0)."""
+    import torch
+
+    box = BOXES[0]
+    rep = Replica(box, [], 3)
+    rho, u = G.random_small_flow(box, seed=11)
+    V = box.nodes
+    solid = O.solid_mask(box)
+    w = O.equilibrium_populations(box, np.full(V, box.rho0), np.zeros((3, V)))[:, 0]
+    with gpu_sim([rep], MDParams(), storage, rho, u, block_size=128, mapping=MAPPINGS[mapping]) as sim:
+        sim.step(2, coupled=False)
+        torch.cuda.synchronize()
+        dt = torch.float32 if storage == F32 else torch.int16
+        bufs = [t.view(dt)[: 19 * V].reshape(19, V).cpu().numpy() for t in sim._tensors[:2]]
+    for b in bufs:
+        if storage == F32:
+            want = (w.astype(np.float32) * np.float32(box.rho0))[:, None]
+            assert np.allclose(b[:, solid], want, rtol=1e-7, atol=0)
+        else:
+            assert np.all(b[:, solid] == 0)
+    assert solid.sum() > 0
+
+
 def test_init_populations_roundtrip():
     box = BOXES[0]
     rep = Replica(box, [], 0)
