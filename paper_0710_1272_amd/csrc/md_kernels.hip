@@ -1494,13 +1494,16 @@ __device__ __forceinline__ unsigned fx_hash(unsigned long long k, unsigned mask)
     return (unsigned)k & mask;
 }
 
-// Pass 1, one thread per bead: the table entry of every fluid node of the start-of-step
+// Pass 1: the table entry of every fluid node of the start-of-step
 // stencil (linear probing; the table holds at most 8 nodes a bead in 16 slots a bead, so a
-// free slot is always found), then 18 integer atomic adds into it.
+// free slot is always found), then 18 integer atomic adds into it; eight lanes a bead.
 template <class Real>
 __global__ __launch_bounds__(64) void k_spread_tri_fx(const Replica* __restrict__ reps, BeadPtrs<Real> b,
                                                       RunState* st) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    // eight lanes a bead, lane c inserting stencil node c (integer sums: the order of the
+    // lanes' adds does not matter)
+    const int lane8 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = lane8 >> 3, c = lane8 & 7;
     if (i >= b.ntot) return;
     const int NT = b.ntot;
     const Replica& R = reps[b.rep_of[i]];
@@ -1511,9 +1514,9 @@ __global__ __launch_bounds__(64) void k_spread_tri_fx(const Replica* __restrict_
     trilinear_axes(R, r, lo, w1);
     const unsigned mask = b.hcap - 1;
     unsigned flags = 0;
-    for (int c = 0; c < 8; ++c) {
+    do {
         const int g[3] = {lo[0][c & 1], lo[1][(c >> 1) & 1], lo[2][(c >> 2) & 1]};
-        if (is_solid(R, g[0], g[1], g[2])) continue;
+        if (is_solid(R, g[0], g[1], g[2])) break;
         const double w = w1[0][c & 1] * w1[1][(c >> 1) & 1] * w1[2][(c >> 2) & 1];
         const unsigned long long key =
             (unsigned long long)(R.pop_base + g[0] + (long long)R.nx * (g[1] + (long long)R.ny * g[2])) + 1ull;
@@ -1530,7 +1533,7 @@ __global__ __launch_bounds__(64) void k_spread_tri_fx(const Replica* __restrict_
         }
         if (!found) {
             flags |= LB_ERR_NONFINITE;
-            continue;
+            break;
         }
         md_for_pops([&](auto P) {
             constexpr int p = decltype(P)::value;
@@ -1548,7 +1551,7 @@ __global__ __launch_bounds__(64) void k_spread_tri_fx(const Replica* __restrict_
                 }
             }
         });
-    }
+    } while (false);
     if (flags) atomicOr(&st->err, flags);
 }
 
@@ -1762,7 +1765,7 @@ template <int S>
 static hipError_t launch_spread_fx_t(const Context& c, void* dst, bool bump, hipStream_t s) {
     using Real = typename MDReal<S>::type;
     const BeadPtrs<Real> b = *(const BeadPtrs<Real>*)c.bead_ptrs;
-    const int grid = (c.ntot_beads + 63) / 64;
+    const int grid = (8 * c.ntot_beads + 63) / 64;  // eight lanes a bead
     hipLaunchKernelGGL((k_spread_tri_fx<Real>), dim3(grid > 0 ? grid : 1), dim3(64), 0, s, c.d_reps, b, c.d_state);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
