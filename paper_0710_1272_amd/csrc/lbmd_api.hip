@@ -472,45 +472,66 @@ int init_populations(Context& c, const lbmd_config* cfg) {
 }
 
 int autotune(Context& c) {
-    hipEvent_t e0, e1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    struct EventGuard {
+        hipEvent_t* a;
+        hipEvent_t* b;
+        ~EventGuard() {
+            if (*a) (void)hipEventDestroy(*a);
+            if (*b) (void)hipEventDestroy(*b);
+        }
+    } guard{&e0, &e1};
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    float best = 1e30f;
-    int best_block = c.lat.block, best_chunk = c.lat_chunk, best_map = c.lat.mapping;
+    struct Shape {
+        int map, block, chunk;
+        float ms;
+    };
+    std::vector<Shape> shapes;
     bool shifted = false;
     for (const Replica& R : c.reps) shifted = shifted || R.x_shift != 0;
     for (int map : {0, 1, 2, 3})
-    for (int b : {128, 256, 512}) {
-        if (map == 2 && !shifted) continue;  // the same launches as the flat mapping
-        for (int chunk : {-1, 0, 16, 64}) {
-            int rc = set_lattice_shape(c, b, map);
-            if (rc != LB_OK) return rc;
-            c.lat_chunk = chunk;
-            HIP_TRY(launch_stream_collide(c, c.pops[c.cur], c.pops[1 - c.cur], false, c.stream));
-            // best of three rounds of 10 back-to-back launches (short kernels are noisy)
-            float ms = 1e30f;
-            for (int round = 0; round < 3; ++round) {
-                HIP_TRY(hipEventRecord(e0, c.stream));
-                for (int k = 0; k < 10; ++k)
-                    HIP_TRY(launch_stream_collide(c, c.pops[c.cur], c.pops[1 - c.cur], false, c.stream));
-                HIP_TRY(hipEventRecord(e1, c.stream));
-                HIP_TRY(hipEventSynchronize(e1));
-                float t = 0;
-                HIP_TRY(hipEventElapsedTime(&t, e0, e1));
-                ms = std::min(ms, t);
-            }
-            if (ms < best) {
-                best = ms;
-                best_block = b;
-                best_chunk = chunk;
-                best_map = map;
-            }
+        for (int b : {128, 256, 512}) {
+            if (map == 2 && !shifted) continue;  // the same launches as the flat mapping
+            for (int chunk : {-1, 0, 16, 64}) shapes.push_back({map, b, chunk, 1e30f});
         }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    c.lat_chunk = best_chunk;
-    return set_lattice_shape(c, best_block, best_map);
+    // `reps` back-to-back launches of one shape, best of `rounds`, in ms per launch
+    auto time_shape = [&](Shape& sh, int reps, int rounds) -> int {
+        int rc = set_lattice_shape(c, sh.block, sh.map);
+        if (rc != LB_OK) return rc;
+        c.lat_chunk = sh.chunk;
+        HIP_TRY(launch_stream_collide(c, c.pops[c.cur], c.pops[1 - c.cur], false, c.stream));
+        float ms = 1e30f;
+        for (int round = 0; round < rounds; ++round) {
+            HIP_TRY(hipEventRecord(e0, c.stream));
+            for (int k = 0; k < reps; ++k)
+                HIP_TRY(launch_stream_collide(c, c.pops[c.cur], c.pops[1 - c.cur], false, c.stream));
+            HIP_TRY(hipEventRecord(e1, c.stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            float t = 0;
+            HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+            ms = std::min(ms, t / reps);
+        }
+        sh.ms = ms;
+        return LB_OK;
+    };
+    // a short pass over every shape (about 1 ms of launches each, at least 2), then the four
+    // fastest timed again as best of three rounds of 10 launches (short kernels are noisy):
+    // a large box spends a few launches per shape instead of 31
+    int rc = time_shape(shapes[0], 2, 1);
+    if (rc != LB_OK) return rc;
+    const int reps1 = std::max(2, std::min(10, (int)(1.0f / std::max(shapes[0].ms, 1e-3f))));
+    for (Shape& sh : shapes)
+        if ((rc = time_shape(sh, reps1, 1)) != LB_OK) return rc;
+    std::stable_sort(shapes.begin(), shapes.end(), [](const Shape& a, const Shape& b) { return a.ms < b.ms; });
+    const size_t finalists = std::min<size_t>(4, shapes.size());
+    for (size_t k = 0; k < finalists; ++k)
+        if ((rc = time_shape(shapes[k], 10, 3)) != LB_OK) return rc;
+    size_t best = 0;
+    for (size_t k = 1; k < finalists; ++k)
+        if (shapes[k].ms < shapes[best].ms) best = k;
+    c.lat_chunk = shapes[best].chunk;
+    return set_lattice_shape(c, shapes[best].block, shapes[best].map);
 }
 
 // Lanes per bead of the bead kernel: times coupled-mode launches (interpolation and M
