@@ -4,8 +4,8 @@ trilinear spread it selects.
 * Bitwise: two contexts of one configuration (autotuned, graph-launched, 20 coupled steps of
   a dense chain with crowders on a pore box, where many stencils and nodes are shared) give
   identical populations, positions, velocities and Fbar, for the nearest-node and trilinear
-  stencils in FP32, FP16 and BF16 storage; a third context with another lattice launch shape
-  (block size and thread mapping) gives the same bits too.
+  stencils in FP32, FP16 and BF16 storage; two more contexts with other lattice launch shapes
+  (block size and thread mapping: row segments, two nodes per lane) give the same bits too.
 * Parity: the fixed-point spread (each contribution rounded once to a multiple of 2^-48,
   sums exact) against the oracle's FP64 spread, over 15 coupled steps (FP64, FP32) and
   10 steps in 16-bit storage, at the tolerances of the floating-point spread; and fluid +
@@ -62,12 +62,15 @@ def test_two_runs_bitwise_equal(stencil, storage):
     rho, u = G.random_small_flow(rep.box, 21, du=0.01)
     a = _run(rep, md, storage, beads, rho, u, 20, flags=_flags())
     b = _run(rep, md, storage, beads, rho, u, 20, flags=_flags())
-    # another lattice launch shape: per-node results do not depend on it
+    # other lattice launch shapes (row segments; two nodes per lane): per-node results do not
+    # depend on them
     c = _run(rep, md, storage, beads, rho, u, 20, flags=_flags(False), block_size=128, mapping=2)
-    log(f"  {['ngp', 'trilinear'][stencil]} {WC.STORE_NAMES[storage]}: shapes {a['shape']} / {c['shape']}")
-    for x in (a, b, c):
+    d = _run(rep, md, storage, beads, rho, u, 20, flags=_flags(False), block_size=256, mapping=4)
+    log(f"  {['ngp', 'trilinear'][stencil]} {WC.STORE_NAMES[storage]}: shapes {a['shape']} / {c['shape']} / "
+        f"{d['shape']}")
+    for x in (a, b, c, d):
         assert x["st"][0] == 0
-    for other in (b, c):
+    for other in (b, c, d):
         assert np.array_equal(a["f"], other["f"])
         for k in range(2):
             assert np.array_equal(a["rv"][k], other["rv"][k])

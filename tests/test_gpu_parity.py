@@ -385,13 +385,14 @@ def test_momentum_exchange_conserves_total_fp64():
     assert np.allclose(p1, p0, rtol=0, atol=1e-12)
 
 
-def test_batched_replicas_match_single():
+@pytest.mark.parametrize("mapping", ["flat", "flat2"])
+def test_batched_replicas_match_single(mapping):
     md = MDParams()
     reps = [Replica(WC.pore_box(48, 48, 48), [30], 101), Replica(WC.pore_box(64, 64, 64), [55], 102),
             Replica(WC.pore_box(80, 80, 80), [20], 103)]
     beads = [G.replica_beads(r, md) for r in reps]
-    log("batched == single, 10 coupled steps, fp32")
-    with gpu_sim(reps, md, F32, beads=np.concatenate(beads)) as sim:
+    log(f"batched == single, 10 coupled steps, fp32, batch mapped {mapping}")
+    with gpu_sim(reps, md, F32, beads=np.concatenate(beads), block_size=256, mapping=MAPPINGS[mapping]) as sim:
         sim.step(10)
         fb = [sim.populations(k) for k in range(3)]
         rb = [sim.beads(k)[0] for k in range(3)]

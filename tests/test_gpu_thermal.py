@@ -35,13 +35,14 @@ def _fluid(box):
 
 @pytest.mark.parametrize("storage,tol", [(F64, 1e-11), (F32, 1e-5)], ids=["f64", "f32"])
 @pytest.mark.parametrize("name", list(BOXES))
-def test_lattice_steps_with_thermal_source(name, storage, tol):
+@pytest.mark.parametrize("mapping", [1, 4], ids=["flat", "flat2"])  # LB_MAP_FLAT, LB_MAP_FLAT2
+def test_lattice_steps_with_thermal_source(mapping, name, storage, tol):
     box = BOXES[name]
     rep = Replica(box, [], 0x1234_5678_9ABC)
     rho, u = G.random_small_flow(box, 8, du=0.01)
     ora = oracle_sim(rep, MDParams(), rho, u, step0=3)
     ora.step(12, coupled=False)
-    with gpu_sim([rep], MDParams(), storage, rho, u, step0=3) as sim:
+    with gpu_sim([rep], MDParams(), storage, rho, u, step0=3, block_size=128, mapping=mapping) as sim:
         sim.step(12, coupled=False)
         f = sim.populations()
         err_word, step = sim.status()
