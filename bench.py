@@ -546,8 +546,11 @@ def main():
                      "note": "achieved = 2 x 19 x 4 B per fluid node / the lattice kernel's average duration "
                              "(HIP events on its launch stream); coupled_step_frac = the same bytes / the "
                              "timed coupled step; same_pattern_gbs = the sweep's loads and stores without "
-                             "arithmetic (lb_pattern_copy, same launch shape); the bead kernel takes "
-                             f"{md_avg * 1e6:.0f} us per step beside the sweep"},
+                             "arithmetic (lb_pattern_copy, same launch shape); traffic = FETCH_SIZE + "
+                             "WRITE_SIZE per launch from the committed counter runs (flat mapping, 256-thread "
+                             "blocks, contiguous XCD ranges; null if the kernel source changed since); the bead "
+                             f"kernel alone takes {md_avg * 1e6:.0f} us per step (md_step, events), hidden "
+                             "under the sweep in the coupled step"},
         "error_word": err_word,
         "paper_context": "0.262 MLUPS coupled (N=100, 80x40x40 box) on a serial 2 GHz Opteron",
     }
