@@ -184,7 +184,12 @@ typedef struct lbmd_config {
 #define LB_XCD_CONTIGUOUS (-2) /* each XCD takes one contiguous eighth of the tiles */
 
 /* Device buffers.  Either all NULL-free (caller-owned, sizes from
- * lb_required_bytes) or the whole struct pointer NULL (library-owned). */
+ * lb_required_bytes) or the whole struct pointer NULL (library-owned).
+ * Population buffer layout: the replicas' blocks one after another, each [19][S] elements of
+ * the storage type, population p of node n (linear index x + nx (y + ny z)) at p S + n, with
+ * the plane stride S = lb_plane_stride(replica, storage) >= V (elements n >= V of a plane are
+ * padding that no call reads or writes).  The slots hold post-collision values of the pull
+ * scheme (Sec. II Eq. lbe), FP16/BF16 as deviations from w_p rho0 scaled per weight class. */
 typedef struct lbmd_buffers {
     void* pops[2]; /* device, lb_required_bytes(cfg, LB_BUF_POPS) bytes each, 256-byte aligned */
     void* beads;   /* device, lb_required_bytes(cfg, LB_BUF_BEADS) bytes, 256-byte aligned */
@@ -303,9 +308,10 @@ int lb_moments_range(lbmd_ctx* ctx, int replica, unsigned what, long long node0,
  * to a static device array of the library: 1 MiB on each GPU it runs on, held until the process
  * ends and shared by every call on that GPU, so calls that overlap in time on one GPU (other
  * streams or host threads) race and return wrong sums.
- *   pops:       device: the replica's [19][V] block of a population buffer in `storage`, as
- *               lb_init lays it out (the current state is buffer pops[0] after an even number
- *               of lattice updates since lb_init); read only; aligned to its element size
+ *   pops:       device: the replica's [19][S] block of a population buffer in `storage` (S =
+ *               lb_plane_stride(rep, storage)), as lb_init lays it out (the current state is
+ *               buffer pops[0] after an even number of lattice updates since lb_init); read
+ *               only; aligned to its element size
  *   storage:    LB_STORE_*
  *   rep:        host: the replica's box, faces, walls and rho0, read during the call (its chains
  *               are ignored)
@@ -317,6 +323,14 @@ int lb_moments_range(lbmd_ctx* ctx, int replica, unsigned what, long long node0,
  * more than 2^27 nodes (the array holds 32768 blocks of partial sums, one per 4096 nodes), and
  * LB_EDEVICE for a launch error. */
 int lb_conserved_noalloc(const void* pops, int storage, const lbmd_replica* rep, double* out4, void* hip_stream);
+
+/* Plane stride S (elements) of a replica's population block in `storage`: the smallest odd
+ * multiple of 256 bytes at least 12032 bytes beyond the V nodes of a plane, so that the 19
+ * planes of a sweep (Sec. II Eq. lbe) do not start a multiple of a large power of two apart,
+ * which puts their streams on the same HBM channels.
+ * Returns -1 (with lb_last_error_message set) for a NULL replica, unknown storage or a
+ * non-positive box size. */
+long long lb_plane_stride(const lbmd_replica* rep, int storage);
 
 /* Lattice-kernel launch shape in use (threads per block). */
 int lb_block_size(const lbmd_ctx* ctx);

@@ -133,7 +133,7 @@ __device__ __forceinline__ void gather19(
         if constexpr (RAW) return v;
         else return C::load_raw(v);
     };
-    const long long V = R.V;
+    const long long V = R.S;  // plane stride
     const int nx = R.nx, nxy = R.nx * R.ny;
     const T* __restrict__ base = src + R.pop_base;
     if constexpr (KIND == G_GENERIC) {
@@ -298,7 +298,7 @@ __device__ __forceinline__ void gather_row(const Replica& R, const typename Code
                                            int idx, int x, int y, int z, typename Codec<S>::R* f) {
     using C = Codec<S>;
     using T = typename C::T;
-    const long long V = R.V;
+    const long long V = R.S;  // plane stride
     const int nx = R.nx, ny = R.ny, nz = R.nz, nxy = R.nx * R.ny;
     const T* __restrict__ base = src + R.pop_base;
     const bool xlo = x == 0, xhi = x == nx - 1, fsx = R.fs[0] != 0;
@@ -572,7 +572,7 @@ __global__ __launch_bounds__(BLOCK) void k_stream_collide(const Replica* __restr
     else relax_node<S, TH>(R, f, idx, st);
 
     typename C::T* __restrict__ out = dst + R.pop_base + idx;
-    const long long V = R.V;
+    const long long V = R.S;  // plane stride
     // non-temporal stores keep a box larger than the last-level cache from evicting the
     // next step's sources; a box that fits it is better left cached for the next sweep
     if constexpr (NT) {
@@ -664,7 +664,7 @@ __global__ __launch_bounds__(BLOCK) void k_stream_collide_2n(const Replica* __re
         }
     });
 
-    const long long V = R.V;
+    const long long V = R.S;  // plane stride
     typename C::T* __restrict__ out = dst + R.pop_base;
     auto finish = [&](Rl* f, int idx, bool fluid) {
         if (fluid) relax_node<S, TH>(R, f, idx, st);
@@ -692,7 +692,7 @@ __global__ __launch_bounds__(BLOCK) void k_pattern(const Replica* __restrict__ r
     const int tile = xcd_tile(blockIdx.x, gridDim.x, xcd_chunk);
     const int r = replica_of_tile(prefix, n_reps, tile);
     const Replica& R = reps[r];
-    const long long V = R.V;
+    const long long V = R.V, PS = R.S;
     const long long n = (long long)(tile - prefix[r]) * BLOCK + threadIdx.x;
     if (n >= V) return;
     const T* __restrict__ base = src + R.pop_base;
@@ -704,12 +704,12 @@ __global__ __launch_bounds__(BLOCK) void k_pattern(const Replica* __restrict__ r
         long long s = n - (cx_of(p) + cy_of(p) * nx + cz_of(p) * nxy);
         if (s < 0) s += V;
         else if (s >= V) s -= V;
-        v[p] = base[(long long)p * V + s];
+        v[p] = base[(long long)p * PS + s];
     });
     for_pops([&](auto P) {
         constexpr int p = decltype(P)::value;
-        if constexpr (NT) __builtin_nontemporal_store(v[p], out + (long long)p * V + n);
-        else out[(long long)p * V + n] = v[p];
+        if constexpr (NT) __builtin_nontemporal_store(v[p], out + (long long)p * PS + n);
+        else out[(long long)p * PS + n] = v[p];
     });
 }
 
@@ -748,7 +748,7 @@ __global__ __launch_bounds__(256) void k_init(const Replica* __restrict__ reps, 
     const Replica& R = reps[r];
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= R.V) return;
-    const long long V = R.V;
+    const long long V = R.V;  // the given fields are dense [19][V] / [3][V]
     const int sx = s % R.nx, sy = (s / R.nx) % R.ny, sz = s / (R.nx * R.ny);
     const bool solid = is_solid(R, sx, sy, sz);
     typename C::T* out = dst + R.pop_base + s;
@@ -770,7 +770,7 @@ __global__ __launch_bounds__(256) void k_init(const Replica* __restrict__ reps, 
             val = wanted(p, x);
         }
         if constexpr (C::deviation) val -= w_of<double>(q) * R.rho0;
-        out[(long long)q * V] = C::template store<q>((typename C::R)val);
+        out[(long long)q * R.S] = C::template store<q>((typename C::R)val);
     });
 }
 
@@ -782,7 +782,7 @@ template <int S>
 __device__ __forceinline__ void gather_f64(const Replica& R, const typename Codec<S>::T* __restrict__ src,
                                            int x, int y, int z, double* f) {
     using C = Codec<S>;
-    const long long V = R.V;
+    const long long V = R.S;  // plane stride
     for_pops([&](auto P) {
         constexpr int p = decltype(P)::value;
         int q;

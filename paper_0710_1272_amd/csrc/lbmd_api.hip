@@ -52,6 +52,19 @@ size_t store_size(int storage) {
     }
 }
 
+// Population plane stride (elements) of a replica of V nodes.  Plane starts a multiple of
+// a large power of two apart (a 512^3 box: 2^29 bytes in FP32) put the same offset of all
+// 19 planes on the same HBM channels, so that the 19 read and 19 write streams of a sweep
+// queue on a few channels at a time.  The stride is an odd multiple of 256 bytes (every
+// plane starts on a 256-byte boundary, so whole-wave stores stay whole lines) at least
+// 47 x 256 bytes beyond the plane: on MI355X a 19-read + 19-write pull copy then ran
+// 7-14 % faster than with unpadded planes (512^3 and 256x128x128 boxes, 4- and 2-byte
+// elements).
+long long plane_stride(long long V, size_t elem) {
+    const long long units = ((V * (long long)elem + 255) / 256 + 47) | 1;  // 256-byte units
+    return units * 256 / (long long)elem;
+}
+
 size_t real_size(int storage) { return storage == LB_STORE_F64 ? 8 : 4; }
 
 const int kBlockSizes[] = {64, 128, 256, 512, 1024};
@@ -60,6 +73,7 @@ const long long kStageNodes = 1 << 20;
 
 struct Totals {
     long long nodes = 0;
+    long long pop_elems = 0;  // 19 S summed over replicas (one population buffer)
     int beads = 0, max_beads = 0, max_V = 0;
 };
 
@@ -69,6 +83,7 @@ Totals totals(const lbmd_config* cfg) {
         const lbmd_replica& R = cfg->replicas[r];
         const long long V = (long long)R.nx * R.ny * R.nz;
         t.nodes += V;
+        t.pop_elems += 19 * plane_stride(V, store_size(cfg->storage));
         t.max_V = std::max<long long>(t.max_V, V);
         int nb = 0;
         for (int c = 0; c < R.n_chains; ++c) nb += R.chain_len[c];
@@ -103,12 +118,13 @@ std::string replica_problem(const lbmd_replica& R) {
     return "";
 }
 
-Replica make_replica(const lbmd_replica& in) {
+Replica make_replica(const lbmd_replica& in, size_t elem) {
     Replica R{};
     R.nx = in.nx;
     R.ny = in.ny;
     R.nz = in.nz;
     R.V = in.nx * in.ny * in.nz;
+    R.S = (int)plane_stride(R.V, elem);
     for (int a = 0; a < 3; ++a) R.fs[a] = in.bc[a] == LB_BC_FREESLIP ? 1 : 0;
     R.n_walls = in.n_walls;
     R.wzone_lo = 1 << 30;
@@ -231,7 +247,9 @@ int lb_validate_config(const lbmd_config* cfg) {
         const std::string why = replica_problem(R);
         if (!why.empty()) return fail(LB_EINVAL, at + why);
         // the lattice kernel addresses one population of a replica with 32-bit byte offsets
-        if ((long long)R.nx * R.ny * R.nz * (long long)store_size(cfg->storage) > (1LL << 32))
+        const long long nodes = (long long)R.nx * R.ny * R.nz;
+        if (nodes * (long long)store_size(cfg->storage) > (1LL << 32) ||
+            plane_stride(nodes, store_size(cfg->storage)) > 0x7FFFFFFFLL)
             return fail(LB_EINVAL, at + "one population of the box exceeds 4 GiB (FP64 storage: at most 2^29 nodes)");
         if (R.n_chains < 0 || (R.n_chains > 0 && !R.chain_len))
             return fail(LB_EINVAL, at + "chain_len missing");
@@ -284,7 +302,7 @@ size_t lb_required_bytes(const lbmd_config* cfg, int which) {
     if (lb_validate_config(cfg) != LB_OK) return 0;
     const Totals t = totals(cfg);
     switch (which) {
-        case LB_BUF_POPS: return align256((size_t)19 * (size_t)t.nodes * store_size(cfg->storage));
+        case LB_BUF_POPS: return align256((size_t)t.pop_elems * store_size(cfg->storage));
         case LB_BUF_BEADS:
             return bead_layout(t.beads, cfg->n_replicas, real_size(cfg->storage), obs_rows(cfg),
                                t.beads > 0 && cfg->md.stencil == LB_STENCIL_TRILINEAR)
@@ -734,7 +752,7 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
 
     const Totals t = totals(cfg);
     c.total_nodes = t.nodes;
-    c.pop_elems = 19 * t.nodes;
+    c.pop_elems = t.pop_elems;
     c.ntot_beads = t.beads;
     c.max_beads = t.max_beads;
     c.max_V = t.max_V;
@@ -747,10 +765,10 @@ int lb_init(const lbmd_config* cfg, const lbmd_buffers* bufs, void* hip_stream, 
     int bead0 = 0;
     for (int r = 0; r < cfg->n_replicas; ++r) {
         const lbmd_replica& in = cfg->replicas[r];
-        Replica R = make_replica(in);
+        Replica R = make_replica(in, store_size(cfg->storage));
         R.x_shift = wall_x_shift(R, store_size(cfg->storage));
         R.pop_base = pop_base;
-        pop_base += 19LL * R.V;
+        pop_base += 19LL * R.S;
         int nb = 0;
         for (int ch = 0; ch < in.n_chains; ++ch) nb += in.chain_len[ch];
         R.bead0 = bead0;
@@ -1021,6 +1039,15 @@ size_t lb_moments_bytes(const lbmd_ctx* ctx, int replica, unsigned what) {
     }
 }
 
+long long lb_plane_stride(const lbmd_replica* rep, int storage) {
+    const size_t elem = store_size(storage);
+    if (!rep || !elem || rep->nx < 1 || rep->ny < 1 || rep->nz < 1) {
+        fail(LB_EINVAL, !rep ? "rep is NULL" : !elem ? "unknown storage" : "box sizes must be >= 1");
+        return -1;
+    }
+    return plane_stride((long long)rep->nx * rep->ny * rep->nz, elem);
+}
+
 int lb_block_size(const lbmd_ctx* ctx) { return ctx ? ctx->c.lat.block : 0; }
 
 int lb_launch_shape(const lbmd_ctx* ctx, int* block, int* mapping, int* xcd_order, int* nt_stores) {
@@ -1261,8 +1288,8 @@ extern "C" int lb_conserved_noalloc(const void* pops, int storage, const lbmd_re
     double* partials = nullptr;
     const int rc = scratch_on_current_device(&partials);
     if (rc != LB_OK) return rc;
-    // pops is the replica's own [19][V] block: its description keeps pop_base = 0
-    const Replica R = make_replica(*rep);
+    // pops is the replica's own [19][S] block: its description keeps pop_base = 0
+    const Replica R = make_replica(*rep, elem);
     HIP_TRY(launch_conserved_desc(R, storage, pops, partials, (int)nblk, out4, (hipStream_t)hip_stream));
     return LB_OK;
 }

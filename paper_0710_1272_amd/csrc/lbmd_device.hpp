@@ -172,12 +172,13 @@ __host__ __device__ inline uint32_t fdiv(uint32_t n, const FastDiv& f) {
 // ---------------------------------------------------------------------------------
 struct Replica {
     int nx, ny, nz, V;
+    int S;              // population plane stride in elements (S >= V, see plane_stride)
     int fs[3];          // 1 if the axis has free-slip faces, 0 if periodic
     int n_walls;
     int wall[LB_MAX_WALLS][6];
     int wzone_lo, wzone_hi;  // x range within one node of any wall (lanes that need solid checks)
     int x_shift;        // shifted flat mapping: position n of a row holds x = (n + x_shift) mod nx
-    long long pop_base; // element offset of this replica's [19][V] block
+    long long pop_base; // element offset of this replica's [19][S] block
     int bead0, n_beads;
     uint32_t seed_lo, seed_hi;
     double omega, rho0;
@@ -377,7 +378,7 @@ struct BeadPtrs {
     int* node;          // [Ntot] nearest node (within the replica), -1 on solid
     unsigned char* bond_next;  // [Ntot] 1 if bead i and i+1 are bonded
     long long* agg_at;  // [2][Ntot]: element offset of population 0 at the node a bead leads
-                        // (pop_base + node, else -1), and the replica's V (population stride)
+                        // (pop_base + node, else -1), and the replica's plane stride S
     Real* agg_f;        // [3][Ntot] summed Fbar of the beads sharing the node a bead leads
     int* rep_of;        // [Ntot] replica of each bead
     double* diag;       // [n_replicas][8]: N_T, t_done, com x,y,z, last step, list builds,

@@ -51,7 +51,7 @@ struct Context {
     lbmd_md_params md_params{};
     MDDev md{};
     long long total_nodes = 0;         // sum of V over replicas
-    long long pop_elems = 0;           // 19 * total_nodes
+    long long pop_elems = 0;           // 19 S summed over replicas (one population buffer)
     int ntot_beads = 0;
     int max_beads = 0;
     int max_V = 0;
@@ -127,7 +127,7 @@ hipError_t launch_conserved(const Context& c, int r, const void* src, double* d_
 hipError_t launch_conserved_desc(const Replica& R, int storage, const void* src, double* partials, int nblk,
                                  double* out4, hipStream_t s);
 // the kernel-side description of one replica (pop_base, bead0 and x_shift are left 0)
-Replica make_replica(const lbmd_replica& in);
+Replica make_replica(const lbmd_replica& in, size_t elem);
 // host-side checks of one replica's box, faces, walls, tau, rho0 and fluid_kT; "" if valid
 std::string replica_problem(const lbmd_replica& R);
 hipError_t launch_md(const Context& c, const void* cur, int mode, hipStream_t s);

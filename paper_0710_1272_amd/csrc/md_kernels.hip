@@ -209,7 +209,7 @@ __device__ __forceinline__ void node_moments(const Replica& R, const void* cur, 
         constexpr int p = decltype(P)::value;
         int q;
         const int s = pull_source<p>(R, g[0], g[1], g[2], &q);
-        Real fp = (Real)C::template load<p>(src[R.pop_base + (long long)q * R.V + s]);
+        Real fp = (Real)C::template load<p>(src[R.pop_base + (long long)q * R.S + s]);
         if constexpr (C::deviation) fp += w_of<Real>(p) * (Real)R.rho0;
         m += fp;
         if constexpr (cx_of(p) != 0) jx += Real(cx_of(p)) * fp;
@@ -1188,7 +1188,7 @@ __global__ __launch_bounds__(MAXT) void k_md(MDKArgs<Real> a, int storage) {
         if (gl == 0) {
             const int gi = b0 + i;
             a.b.agg_at[gi] = lead ? R.pop_base + me : -1;
-            a.b.agg_at[NT + gi] = R.V;
+            a.b.agg_at[NT + gi] = R.S;
 #pragma unroll
             for (int c = 0; c < 3; ++c) a.b.agg_f[c * NT + gi] = lead ? s[c] : Real(0);
         }
@@ -1450,7 +1450,7 @@ __global__ __launch_bounds__(256) void k_spread_tri(const Replica* __restrict__ 
     int lo[3][2];
     double w1[3][2];
     trilinear_axes(R, r, lo, w1);
-    const long long V = R.V;
+    const long long V = R.S;  // plane stride
     {
         const int g[3] = {lo[0][c & 1], lo[1][(c >> 1) & 1], lo[2][(c >> 2) & 1]};
         if (is_solid(R, g[0], g[1], g[2])) return;
@@ -1570,7 +1570,7 @@ __global__ __launch_bounds__(256) void k_spread_fx_apply(const Replica* __restri
     if (h >= b.hcap) return;
     const unsigned long long key = b.hkey[h];
     if (key == 0ull) return;
-    const long long V = reps[b.hrep[h]].V;
+    const long long V = reps[b.hrep[h]].S;  // plane stride
     typename C::T* __restrict__ base = dst + (long long)(key - 1ull);
     md_for_pops([&](auto P) {
         constexpr int p = decltype(P)::value;

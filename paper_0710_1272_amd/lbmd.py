@@ -37,7 +37,7 @@ LB_STENCIL_NGP, LB_STENCIL_TRILINEAR = 0, 1
 
 EXPORTED = ["lb_required_bytes", "lb_validate_config", "lb_init", "lb_step", "lb_graph_prepare", "lb_couple", "md_step",
             "lb_moments", "lb_moments_bytes", "lb_moments_range", "lb_block_size", "lb_launch_shape", "lb_md_lanes", "lb_destroy",
-            "lb_strerror", "lb_last_error_message", "lb_conserved_noalloc", "lb_pattern_copy"]
+            "lb_strerror", "lb_last_error_message", "lb_conserved_noalloc", "lb_pattern_copy", "lb_plane_stride"]
 
 
 class lbmd_wall(C.Structure):
@@ -116,6 +116,8 @@ def lib():
         L.lb_md_lanes.argtypes = [C.c_void_p]
         L.lb_pattern_copy.argtypes = [C.c_void_p, C.c_int]
         L.lb_conserved_noalloc.argtypes = [C.c_void_p, C.c_int, C.POINTER(lbmd_replica), C.c_void_p, C.c_void_p]
+        L.lb_plane_stride.argtypes = [C.POINTER(lbmd_replica), C.c_int]
+        L.lb_plane_stride.restype = C.c_longlong
         L.lb_destroy.argtypes = [C.c_void_p]
         L.lb_strerror.argtypes = [C.c_int]
         L.lb_strerror.restype = C.c_char_p
@@ -263,6 +265,13 @@ class Simulation:
     @property
     def block_size(self) -> int:
         return lib().lb_block_size(self.ctx)
+
+    def plane_stride(self, replica: int = 0) -> int:
+        """Elements between population planes in the replica's [19][S] block of a buffer."""
+        s = lib().lb_plane_stride(C.byref(self._cfg.reps[replica]), self.storage)
+        if s < 0:
+            raise LBError(LB_EINVAL, "lb_plane_stride")
+        return s
 
     def launch_shape(self):
         b, m, x, nt = C.c_int(), C.c_int(), C.c_int(), C.c_int()

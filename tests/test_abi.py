@@ -1,5 +1,6 @@
 """The C-ABI library loads, exports what include/lbmd.h declares, and validates
 configurations on the host (no device call is made by these functions)."""
+import ctypes as C
 import os
 import re
 
@@ -16,7 +17,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared_functions():
     text = open(os.path.join(ROOT, "include", "lbmd.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(lb_\w+|md_\w+)\s*\(", text, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:(?:const|long|unsigned)\s+)*\w+\**\s+\**(lb_\w+|md_\w+)\s*\(", text,
+                                 flags=re.M)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -48,9 +50,37 @@ def test_named_workloads_are_valid(w):
     assert c.validate() == B.LB_OK, B.lib().lb_last_error_message()
     pops = c.required_bytes(B.LB_BUF_POPS)
     elem = {0: 8, 1: 4, 2: 2, 3: 2}[w.storage]
-    assert pops >= 19 * w.nodes * elem
-    assert pops - 19 * w.nodes * elem < 256
+    strides = [B.lib().lb_plane_stride(C.byref(c.reps[k]), w.storage) for k in range(len(w.replicas))]
+    assert pops == 19 * sum(strides) * elem
     assert c.required_bytes(B.LB_BUF_WORK) > 0 and c.required_bytes(B.LB_BUF_BEADS) > 0
+
+
+@pytest.mark.parametrize("storage", [B.LB_STORE_F64, B.LB_STORE_F32, B.LB_STORE_F16DEV, B.LB_STORE_BF16DEV])
+@pytest.mark.parametrize("dims", [(512, 512, 512), (256, 128, 128), (48, 48, 48), (10, 10, 10), (1, 1, 1),
+                                  (2, 64, 1)])
+def test_plane_stride(storage, dims):
+    """Planes start on 256-byte boundaries, an odd number of 256-byte units apart, and the
+    smallest such stride at least 12032 bytes beyond the plane's nodes."""
+    L = B.lib()
+    rep = B.lbmd_replica()
+    rep.nx, rep.ny, rep.nz = dims
+    elem = {0: 8, 1: 4, 2: 2, 3: 2}[storage]
+    V = dims[0] * dims[1] * dims[2]
+    S = L.lb_plane_stride(C.byref(rep), storage)
+    assert (S * elem) % 256 == 0 and ((S * elem) // 256) % 2 == 1
+    assert S * elem >= V * elem + 12032
+    assert S * elem - 512 < V * elem + 12032
+
+
+def test_plane_stride_rejects_bad_input():
+    L = B.lib()
+    rep = B.lbmd_replica()
+    rep.nx, rep.ny, rep.nz = 8, 8, 8
+    assert L.lb_plane_stride(C.byref(rep), 9) == -1
+    assert b"storage" in L.lb_last_error_message()
+    assert L.lb_plane_stride(None, B.LB_STORE_F32) == -1
+    rep.nz = 0
+    assert L.lb_plane_stride(C.byref(rep), B.LB_STORE_F32) == -1
 
 
 def _rep(**kw):
@@ -113,7 +143,8 @@ def test_no_gpu_needed_for_host_calls():
     # these calls must not touch the device: they work in a CPU-only process
     c = _cfg([_rep()])
     assert c.validate() == B.LB_OK
-    assert c.required_bytes(B.LB_BUF_POPS) == ((19 * 32 * 16 * 16 * 4 + 255) // 256) * 256
+    # 8192 nodes x 4 bytes = 128 units of 256 bytes per plane, + 47 (odd): 175 units a plane
+    assert c.required_bytes(B.LB_BUF_POPS) == 19 * 175 * 256
 
 
 def test_md_lanes_validation():

@@ -68,4 +68,4 @@ def test_matches_lb_moments_twice(storage):
             log(f"    mass {got[0]:.15e} vs {e[0]:.15e}; momentum {got[1:]} vs {e[1:]}")
             assert abs(got[0] - e[0]) <= 1e-12 * e[0]
             assert np.max(np.abs(got[1:] - e[1:])) <= 1e-12 * e[0]
-            offset += 19 * rep.box.nodes * ELEM[storage]
+            offset += 19 * sim.plane_stride(k) * ELEM[storage]
