@@ -96,7 +96,8 @@ def test_batched_replicas_record_independently():
     with gpu_sim(reps, md, F32, beads=np.concatenate(beads), obs_every=2, obs_capacity=10) as sim:
         sim.step(12)
         both = [sim.observables(k)[0] for k in range(2)]
+        lanes = sim.md_lanes  # the lanes per bead set the order of a bead's force sums
     for k, rep in enumerate(reps):
-        with gpu_sim([rep], md, F32, beads=beads[k], obs_every=2, obs_capacity=10) as one:
+        with gpu_sim([rep], md, F32, beads=beads[k], obs_every=2, obs_capacity=10, md_lanes=lanes) as one:
             one.step(12)
             assert np.array_equal(one.observables()[0], both[k])

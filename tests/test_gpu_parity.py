@@ -398,8 +398,11 @@ def test_batched_replicas_match_single(mapping):
         sim.step(10)
         fb = [sim.populations(k) for k in range(3)]
         rb = [sim.beads(k)[0] for k in range(3)]
+        lanes = sim.md_lanes
+    # the lanes per bead (chosen from the largest chain of a context) set the order in which a
+    # bead's forces are summed: each replica alone takes the batch's
     for k, rep in enumerate(reps):
-        with gpu_sim([rep], md, F32, beads=beads[k]) as one:
+        with gpu_sim([rep], md, F32, beads=beads[k], md_lanes=lanes) as one:
             one.step(10)
             assert np.array_equal(one.populations(), fb[k])
             assert np.array_equal(one.beads()[0], rb[k])
