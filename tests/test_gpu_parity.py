@@ -170,6 +170,47 @@ def test_pattern_copy_alternating():
     assert not np.array_equal(f1, f2) and np.all(np.isfinite(f2))
 
 
+@pytest.mark.parametrize("storage", [F64, F32, F16], ids=["f64", "f32", "f16dev"])
+def test_plane_padding_untouched(storage):
+    """Population planes are padded (lb_plane_stride): after lb_init, the elements past each
+    plane's V nodes are written by no kernel of a coupled step (sweep, bead kernel, spread) in
+    either buffer, and the populations read back equal the oracle's whatever those hold."""
+    import torch
+
+    md = MDParams()
+    # V = 6000 and 9792 nodes: neither plane a multiple of 256 bytes in 16-bit storage
+    reps = [Replica(WC.pore_box(30, 20, 10), [6], 21), Replica(WC.pore_box(34, 24, 12), [8], 22)]
+    beads = [G.replica_beads(r, md) for r in reps]
+    elem = {F64: 8, F32: 4, F16: 2}[storage]
+    log(f"plane padding untouched, {WC.STORE_NAMES[storage]}, two replicas, 6 coupled steps")
+    with gpu_sim(reps, md, storage, beads=np.concatenate(beads)) as sim:
+        torch.cuda.synchronize()
+        # a sentinel over every pad element of both buffers after lb_init; nothing may overwrite it
+        off = 0
+        for k, r in enumerate(reps):
+            S, V = sim.plane_stride(k), r.box.nodes
+            assert S >= V and (S * elem) % 256 == 0
+            assert off + 19 * S * elem <= sim._tensors[0].numel()
+            for buf in sim._tensors[:2]:
+                buf[off: off + 19 * S * elem].view(19, S * elem)[:, V * elem:] = 0xA5
+            off += 19 * S * elem
+        sim.step(6)
+        torch.cuda.synchronize()
+        off = 0
+        for k, r in enumerate(reps):
+            S, V = sim.plane_stride(k), r.box.nodes
+            for buf in sim._tensors[:2]:
+                tail = buf[off: off + 19 * S * elem].view(19, S * elem)[:, V * elem:]
+                assert bool(torch.all(tail == 0xA5)), f"replica {k}: a pad element was written"
+            off += 19 * S * elem
+        f = [sim.populations(k) for k in range(2)]
+    for k, r in enumerate(reps):
+        ora = oracle_sim(r, md, beads=beads[k])
+        ora.step(6)
+        tol = {F64: 1e-12, F32: 1e-5, F16: 1e-4}[storage]
+        assert max_rel(f[k], ora.f, _fluid(r.box)) < tol
+
+
 @pytest.mark.parametrize("storage", [F32, F16], ids=["f32", "f16dev"])
 @pytest.mark.parametrize("mapping", list(MAPPINGS))
 def test_solid_slots_hold_rest_values(mapping, storage):
