@@ -133,7 +133,7 @@ __device__ __forceinline__ void gather19(
         if constexpr (RAW) return v;
         else return C::load_raw(v);
     };
-    const long long V = R.S;  // plane stride
+    const long long PS = R.S;  // population plane stride
     const int nx = R.nx, nxy = R.nx * R.ny;
     const T* __restrict__ base = src + R.pop_base;
     if constexpr (KIND == G_GENERIC) {
@@ -143,7 +143,7 @@ __device__ __forceinline__ void gather19(
             const int node = pull_source<p>(R, x, y, z, &q);
             // q differs from p only by reflections or reversal, which keep the weight
             // class, so the codec scale of p applies to slot q
-            f[p] = cv(base[(long long)q * V + node]);
+            f[p] = cv(base[(long long)q * PS + node]);
         });
         return;
     }
@@ -208,7 +208,7 @@ __device__ __forceinline__ void gather19(
         if constexpr (KIND != G_INTERIOR && cx == -1) {
             if (xhi) node -= fsx ? 1 : nx;
         }
-        f[p] = cv(ld32(base + (long long)p * V, node));
+        f[p] = cv(ld32(base + (long long)p * PS, node));
         if constexpr (KIND == G_WALL && p != 0) {
             // source offset -c: neighbour bit 9(1 - c_x) + 3(1 - c_y) + (1 - c_z), or bit
             // (1 - c) of each wall's masks
@@ -226,10 +226,10 @@ __device__ __forceinline__ void gather19(
                 }
             }
             // half-way bounce-back: the node's own population opp(p) of the last collision
-            if (solid) f[p] = cv(ld32(base + (long long)opp_of(p) * V, idx));
+            if (solid) f[p] = cv(ld32(base + (long long)opp_of(p) * PS, idx));
         }
         if constexpr (KIND == G_WALL_PLANE && cx != 0) {
-            if (cx == 1 ? solid_m : solid_p) f[p] = cv(ld32(base + (long long)opp_of(p) * V, idx));
+            if (cx == 1 ? solid_m : solid_p) f[p] = cv(ld32(base + (long long)opp_of(p) * PS, idx));
         }
     });
     if constexpr (KIND != G_INTERIOR) {
@@ -239,7 +239,7 @@ __device__ __forceinline__ void gather19(
             for_pops([&](auto P) {
                 constexpr int p = decltype(P)::value;
                 if constexpr (cx_of(p) == 1)
-                    f[p] = cv(ld32(base + (long long)mirror_of(p, 0) * V,
+                    f[p] = cv(ld32(base + (long long)mirror_of(p, 0) * PS,
                                             idx - (cy_of(p) * nx + cz_of(p) * nxy)));
             });
         }
@@ -247,7 +247,7 @@ __device__ __forceinline__ void gather19(
             for_pops([&](auto P) {
                 constexpr int p = decltype(P)::value;
                 if constexpr (cx_of(p) == -1)
-                    f[p] = cv(ld32(base + (long long)mirror_of(p, 0) * V,
+                    f[p] = cv(ld32(base + (long long)mirror_of(p, 0) * PS,
                                             idx - (cy_of(p) * nx + cz_of(p) * nxy)));
             });
         }
@@ -298,7 +298,7 @@ __device__ __forceinline__ void gather_row(const Replica& R, const typename Code
                                            int idx, int x, int y, int z, typename Codec<S>::R* f) {
     using C = Codec<S>;
     using T = typename C::T;
-    const long long V = R.S;  // plane stride
+    const long long PS = R.S;  // population plane stride
     const int nx = R.nx, ny = R.ny, nz = R.nz, nxy = R.nx * R.ny;
     const T* __restrict__ base = src + R.pop_base;
     const bool xlo = x == 0, xhi = x == nx - 1, fsx = R.fs[0] != 0;
@@ -327,12 +327,12 @@ __device__ __forceinline__ void gather_row(const Replica& R, const typename Code
             if (xhi) node -= fsx ? 1 : nx;
         }
         const int q = mirror_combo<p>(false, fy, fz);  // uniform over the wave
-        f[p] = C::load_raw(ld32(base + (long long)q * V, node));
+        f[p] = C::load_raw(ld32(base + (long long)q * PS, node));
         if constexpr (cx != 0) {
             // free slip: the population with c_x reflected as well, from that node
             if (fsx && (cx == 1 ? xlo : xhi)) {
                 const int m = mirror_combo<p>(true, fy, fz);
-                f[p] = C::load_raw(ld32(base + (long long)m * V, node));
+                f[p] = C::load_raw(ld32(base + (long long)m * PS, node));
             }
         }
         if constexpr (WALL && p != 0) {
@@ -347,7 +347,7 @@ __device__ __forceinline__ void gather_row(const Replica& R, const typename Code
                 solid = solid || (!inpore && x - cx >= w[0] && x - cx <= w[1]);
             }
             // half-way bounce-back: the node's own population opp(p) of the last collision
-            if (solid) f[p] = C::load_raw(ld32(base + (long long)opp_of(p) * V, idx));
+            if (solid) f[p] = C::load_raw(ld32(base + (long long)opp_of(p) * PS, idx));
         }
     });
 }
@@ -572,18 +572,18 @@ __global__ __launch_bounds__(BLOCK) void k_stream_collide(const Replica* __restr
     else relax_node<S, TH>(R, f, idx, st);
 
     typename C::T* __restrict__ out = dst + R.pop_base + idx;
-    const long long V = R.S;  // plane stride
+    const long long PS = R.S;  // population plane stride
     // non-temporal stores keep a box larger than the last-level cache from evicting the
     // next step's sources; a box that fits it is better left cached for the next sweep
     if constexpr (NT) {
         for_pops([&](auto P) {
             constexpr int p = decltype(P)::value;
-            __builtin_nontemporal_store(C::store_raw(f[p]), out + (long long)p * V);
+            __builtin_nontemporal_store(C::store_raw(f[p]), out + (long long)p * PS);
         });
     } else {
         for_pops([&](auto P) {
             constexpr int p = decltype(P)::value;
-            out[(long long)p * V] = C::store_raw(f[p]);
+            out[(long long)p * PS] = C::store_raw(f[p]);
         });
     }
 }
@@ -664,15 +664,15 @@ __global__ __launch_bounds__(BLOCK) void k_stream_collide_2n(const Replica* __re
         }
     });
 
-    const long long V = R.S;  // plane stride
+    const long long PS = R.S;  // population plane stride
     typename C::T* __restrict__ out = dst + R.pop_base;
     auto finish = [&](Rl* f, int idx, bool fluid) {
         if (fluid) relax_node<S, TH>(R, f, idx, st);
         else rest_slots<S>(R, f);
         for_pops([&](auto P) {
             constexpr int p = decltype(P)::value;
-            if constexpr (NT) __builtin_nontemporal_store(C::store_raw(f[p]), out + (long long)p * V + idx);
-            else out[(long long)p * V + idx] = C::store_raw(f[p]);
+            if constexpr (NT) __builtin_nontemporal_store(C::store_raw(f[p]), out + (long long)p * PS + idx);
+            else out[(long long)p * PS + idx] = C::store_raw(f[p]);
         });
     };
     finish(f0, n[0], act[0]);
@@ -782,12 +782,12 @@ template <int S>
 __device__ __forceinline__ void gather_f64(const Replica& R, const typename Codec<S>::T* __restrict__ src,
                                            int x, int y, int z, double* f) {
     using C = Codec<S>;
-    const long long V = R.S;  // plane stride
+    const long long PS = R.S;  // population plane stride
     for_pops([&](auto P) {
         constexpr int p = decltype(P)::value;
         int q;
         const int node = pull_source<p>(R, x, y, z, &q);
-        double v = (double)C::template load<p>(src[R.pop_base + (long long)q * V + node]);
+        double v = (double)C::template load<p>(src[R.pop_base + (long long)q * PS + node]);
         if constexpr (C::deviation) v += w_of<double>(p) * R.rho0;
         f[p] = v;
     });

@@ -1218,7 +1218,7 @@ __global__ __launch_bounds__(256) void k_spread(const Replica* __restrict__ reps
     if (i >= b.ntot) return;
     // one round trip for everything a leader needs: where, stride, force
     const long long at = b.agg_at[i];
-    const long long V = b.agg_at[b.ntot + i];
+    const long long PS = b.agg_at[b.ntot + i];
     const Rl F[3] = {(Rl)b.agg_f[i], (Rl)b.agg_f[b.ntot + i], (Rl)b.agg_f[2 * b.ntot + i]};
     if (at < 0) return;
     typename C::T* __restrict__ base = dst + at;
@@ -1236,7 +1236,7 @@ __global__ __launch_bounds__(256) void k_spread(const Replica* __restrict__ reps
         // leader, so no two threads add to one element and the result is deterministic)
         md_for_pops([&](auto P) {
             constexpr int p = decltype(P)::value;
-            if constexpr (p != 0) (void)unsafeAtomicAdd(&base[(long long)p * V], source(P));
+            if constexpr (p != 0) (void)unsafeAtomicAdd(&base[(long long)p * PS], source(P));
         });
     } else {
         // 16-bit storage: decode, add, re-encode; all 18 moving populations are read
@@ -1244,11 +1244,11 @@ __global__ __launch_bounds__(256) void k_spread(const Replica* __restrict__ reps
         Rl f[Q];
         md_for_pops([&](auto P) {
             constexpr int p = decltype(P)::value;
-            if constexpr (p != 0) f[p] = C::template load<p>(base[(long long)p * V]);
+            if constexpr (p != 0) f[p] = C::template load<p>(base[(long long)p * PS]);
         });
         md_for_pops([&](auto P) {
             constexpr int p = decltype(P)::value;
-            if constexpr (p != 0) base[(long long)p * V] = C::template store<p>(f[p] + source(P));
+            if constexpr (p != 0) base[(long long)p * PS] = C::template store<p>(f[p] + source(P));
         });
     }
 }
@@ -1450,7 +1450,7 @@ __global__ __launch_bounds__(256) void k_spread_tri(const Replica* __restrict__ 
     int lo[3][2];
     double w1[3][2];
     trilinear_axes(R, r, lo, w1);
-    const long long V = R.S;  // plane stride
+    const long long PS = R.S;  // population plane stride
     {
         const int g[3] = {lo[0][c & 1], lo[1][(c >> 1) & 1], lo[2][(c >> 2) & 1]};
         if (is_solid(R, g[0], g[1], g[2])) return;
@@ -1465,9 +1465,9 @@ __global__ __launch_bounds__(256) void k_spread_tri(const Replica* __restrict__ 
                 if constexpr (cz_of(p) != 0) fc += Rl(cz_of(p)) * F[2];
                 const Rl src = -Rl(3) * w_of<Rl>(p) * fc * w;
                 if constexpr (S == LB_STORE_F32 || S == LB_STORE_F64)
-                    (void)unsafeAtomicAdd(&base[(long long)p * V], src);
+                    (void)unsafeAtomicAdd(&base[(long long)p * PS], src);
                 else
-                    atomic_add_dev16<S, p>(&base[(long long)p * V], src);
+                    atomic_add_dev16<S, p>(&base[(long long)p * PS], src);
             }
         });
     }
@@ -1570,7 +1570,7 @@ __global__ __launch_bounds__(256) void k_spread_fx_apply(const Replica* __restri
     if (h >= b.hcap) return;
     const unsigned long long key = b.hkey[h];
     if (key == 0ull) return;
-    const long long V = reps[b.hrep[h]].S;  // plane stride
+    const long long PS = reps[b.hrep[h]].S;  // population plane stride
     typename C::T* __restrict__ base = dst + (long long)(key - 1ull);
     md_for_pops([&](auto P) {
         constexpr int p = decltype(P)::value;
@@ -1579,7 +1579,7 @@ __global__ __launch_bounds__(256) void k_spread_fx_apply(const Replica* __restri
             const long long q = *cell;
             if (q != 0) {
                 const Rl add = (Rl)((double)q * (1.0 / kFxScale));
-                base[(long long)p * V] = C::template store<p>(C::template load<p>(base[(long long)p * V]) + add);
+                base[(long long)p * PS] = C::template store<p>(C::template load<p>(base[(long long)p * PS]) + add);
                 *cell = 0;
             }
         }
