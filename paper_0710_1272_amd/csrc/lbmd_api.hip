@@ -156,7 +156,7 @@ WorkLayout work_layout(int n_reps, int max_V, long long max_stage_nodes) {
     off += align256(sizeof(Replica) * (size_t)n_reps);
     L.state = off;
     off += align256(sizeof(RunState));
-    L.partial_blocks = 2048;  // 8192 waves: enough loads in flight to stream a large box
+    L.partial_blocks = 32768;  // capacity: one block of partial sums per 4096 nodes up to 2^27 nodes
     L.partials = off;
     off += align256(sizeof(double) * (4 * (size_t)L.partial_blocks + 4));
     const long long stage_nodes = std::min<long long>(max_V, max_stage_nodes);
