@@ -481,8 +481,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the other workloads")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the multi-GPU decomposition is a design "
-              "note); --gpus must be 1", file=sys.stderr)
+        print("bench.py: the library runs the coupled step on one GPU; --gpus must be 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
