@@ -146,7 +146,10 @@ typedef struct lbmd_initial_state {
                                    they set the order of the bead-force sums.  The lattice kernel's
                                    launch shape never changes results.  A contribution above 512
                                    in magnitude is dropped and sets LB_ERR_NONFINITE (so that no
-                                   node's 64-bit sum can overflow below 64 contributions) */
+                                   node's 64-bit sum can overflow below 64 contributions).  FP16 and
+                                   BF16 storage take this fixed-point spread with or without the
+                                   flag (it is faster there than a floating-point add into a 16-bit
+                                   element) */
 
 typedef struct lbmd_config {
     int n_replicas;

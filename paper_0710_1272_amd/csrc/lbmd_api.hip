@@ -675,14 +675,15 @@ hipError_t enqueue_step(Context& c, int mode, int cur, hipStream_t main) {
         // and a sweep enqueued ahead of it fills every unit, so that the bead kernel would
         // wait for the sweep's blocks to drain instead of running beside them
         hipError_t e;
+        // the trilinear interpolation (8 x 19 population reads a bead, a launch of its own) goes
+        // on the main stream ahead of the fork, where no sweep competes with its reads: on
+        // 128x64x64 (FP32) it took 19 us beside the sweep and 11 us ahead of it, and the step
+        // fell from 68 to 60 us
+        const bool tri = c.md.stencil == LB_STENCIL_TRILINEAR;
+        if (tri && (e = launch_interp_trilinear(c, src, main)) != hipSuccess) return e;
         if ((e = hipEventRecord(c.ev_fork, main)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(c.side, c.ev_fork, 0)) != hipSuccess) return e;
-        if (c.md.stencil == LB_STENCIL_TRILINEAR) {
-            if ((e = launch_interp_trilinear(c, src, c.side)) != hipSuccess) return e;
-            if ((e = launch_md(c, src, MD_SUBSTEPS, c.side)) != hipSuccess) return e;
-        } else if ((e = launch_md(c, src, MD_COUPLED, c.side)) != hipSuccess) {
-            return e;
-        }
+        if ((e = launch_md(c, src, tri ? MD_SUBSTEPS : MD_COUPLED, c.side)) != hipSuccess) return e;
         if (c.obs_every > 0 && (e = launch_observe(c, false, c.side)) != hipSuccess) return e;
         if ((e = hipEventRecord(c.ev_join, c.side)) != hipSuccess) return e;
         if ((e = launch_stream_collide(c, src, dst, false, main)) != hipSuccess) return e;

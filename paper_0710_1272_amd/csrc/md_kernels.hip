@@ -1409,28 +1409,11 @@ __global__ __launch_bounds__(256) void k_interp_tri(const Replica* __restrict__ 
     }
 }
 
-// 16-bit deviation storage: add to one element by compare-and-swap on the 32-bit word that
-// holds it (decode, add, re-encode; the other half of the word is kept as read)
-template <int S, int P>
-__device__ __forceinline__ void atomic_add_dev16(typename Codec<S>::T* addr, float val) {
-    using T = typename Codec<S>::T;
-    const uintptr_t at = (uintptr_t)addr;
-    unsigned int* word = (unsigned int*)(at & ~(uintptr_t)3);
-    const int sh = (at & 2) ? 16 : 0;
-    unsigned int old = *word, seen;
-    do {
-        seen = old;
-        const T h = __builtin_bit_cast(T, (uint16_t)((seen >> sh) & 0xffffu));
-        const T nh = Codec<S>::template store<P>(Codec<S>::template load<P>(h) + val);
-        const unsigned int nw = (seen & ~(0xffffu << sh)) | ((unsigned int)__builtin_bit_cast(uint16_t, nh) << sh);
-        old = atomicCAS(word, seen, nw);
-    } while (old != seen);
-}
-
-// Step 3 with the trilinear stencil, one thread per bead: -w_c (w_p / c_s^2) Fbar . c_p added
-// to the post-collision populations of every fluid node of the start-of-step stencil.
-// Stencils of nearby beads share nodes, so the adds are atomic (their order, and so the
-// last bits of FP32 sums, can differ between runs).
+// Step 3 with the trilinear stencil, eight lanes a bead (FP32 and FP64 storage): -w_c (w_p /
+// c_s^2) Fbar . c_p added to the post-collision populations of every fluid node of the
+// start-of-step stencil.  Stencils of nearby beads share nodes, so the adds are atomic (their
+// order, and so the last bits of FP32 sums, can differ between runs).  16-bit storage takes
+// the fixed-point spread below.
 template <int S>
 __global__ __launch_bounds__(256) void k_spread_tri(const Replica* __restrict__ reps,
                                                     BeadPtrs<typename MDReal<S>::type> b,
@@ -1464,10 +1447,7 @@ __global__ __launch_bounds__(256) void k_spread_tri(const Replica* __restrict__ 
                 if constexpr (cy_of(p) != 0) fc += Rl(cy_of(p)) * F[1];
                 if constexpr (cz_of(p) != 0) fc += Rl(cz_of(p)) * F[2];
                 const Rl src = -Rl(3) * w_of<Rl>(p) * fc * w;
-                if constexpr (S == LB_STORE_F32 || S == LB_STORE_F64)
-                    (void)unsafeAtomicAdd(&base[(long long)p * PS], src);
-                else
-                    atomic_add_dev16<S, p>(&base[(long long)p * PS], src);
+                (void)unsafeAtomicAdd(&base[(long long)p * PS], src);
             }
         });
     }
@@ -1775,7 +1755,12 @@ static hipError_t launch_spread_fx_t(const Context& c, void* dst, bool bump, hip
 }
 
 hipError_t launch_spread(const Context& c, void* dst, bool bump, hipStream_t s) {
-    if (c.md.stencil == LB_STENCIL_TRILINEAR && c.deterministic) {
+    // the trilinear spread in fixed point when asked for reproducible results, and always in
+    // 16-bit storage: there a floating-point add into one element is a compare-and-swap loop on
+    // its 32-bit word, and the integer atomics and one read-modify-write per node took 23 us
+    // against 44 us on 128x64x64 (N = 100)
+    const bool half = c.storage == LB_STORE_F16DEV || c.storage == LB_STORE_BF16DEV;
+    if (c.md.stencil == LB_STENCIL_TRILINEAR && (c.deterministic || half)) {
         switch (c.storage) {
             case LB_STORE_F64: return launch_spread_fx_t<LB_STORE_F64>(c, dst, bump, s);
             case LB_STORE_F32: return launch_spread_fx_t<LB_STORE_F32>(c, dst, bump, s);
@@ -1788,9 +1773,7 @@ hipError_t launch_spread(const Context& c, void* dst, bool bump, hipStream_t s) 
         switch (c.storage) {
             case LB_STORE_F64: return launch_spread_tri_t<LB_STORE_F64>(c, dst, bump, s);
             case LB_STORE_F32: return launch_spread_tri_t<LB_STORE_F32>(c, dst, bump, s);
-            case LB_STORE_F16DEV: return launch_spread_tri_t<LB_STORE_F16DEV>(c, dst, bump, s);
-            case LB_STORE_BF16DEV: return launch_spread_tri_t<LB_STORE_BF16DEV>(c, dst, bump, s);
-            default: return hipErrorInvalidValue;
+            default: return hipErrorInvalidValue;  // 16-bit storage took the fixed-point path
         }
     }
     switch (c.storage) {
